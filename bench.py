@@ -1,0 +1,177 @@
+"""Throughput of the fused low-level reconstruction on one MI355X.
+
+Workload (the mixed-camera throughput configuration): dual-gain uint16 traces
+of 1855-px x 40-sample, 1764-px x 25-sample and 2048-px x 128-sample cameras
+in ratio 1:3:6, plain ellipse images.  A seeded pool of unique camera events
+(default 3000, about 2.1 GB, far larger than the 256 MB last-level cache) is
+made resident in HBM; one step is one pass of calibration -> cleaning ->
+Hillas over 1e6 camera events streamed through the pool in a seeded random
+order, replayed from a captured HIP graph.  Inputs are resident before the
+timed region starts.
+
+Prints one JSON line: camera-events/s (whole job), with input GB/s (full DL0
+bytes, both gains), the roofline of the fused kernel (algorithmic HBM bytes:
+high-gain trace + low-gain trace of switched pixels + 64-byte record + 12-byte
+descriptor per telescope) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pool, ty, off, target_s=10.0):
+    """The oracle as it stands, on host cores, over a bounded sample of the
+    same descriptor stream (time-bounded: chunks of 1000 events until about
+    target_s seconds of wall time)."""
+    import oracle
+    ocs = [oracle.Camera.from_type(c) for c in pool.cams]
+    threads = max(1, min(16, os.cpu_count() or 1))
+    done, t_used, k = 0, 0.0, 0
+    per = np.array([c.dl0_bytes for c in pool.cams], np.int64)
+    nbytes = 0
+    while t_used < target_s and k < len(ty):
+        sl = slice(k, min(k + 1000, len(ty)))
+        t0 = time.perf_counter()
+        oracle.reconstruct_batch(ocs, ty[sl], pool.blob, off[sl], n_threads=threads)
+        t_used += time.perf_counter() - t0
+        done += sl.stop - sl.start
+        nbytes += int(per[ty[sl]].sum())
+        k = sl.stop
+    return {"value": done / t_used, "unit": "camera-events/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d camera events of the same stream order (C++ FP64 oracle, %d threads, "
+                      "%.1f s wall)" % (done, threads, t_used),
+            "input_GBps": nbytes / t_used / 1e9}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--pool", type=int, default=3000, help="unique camera events resident in HBM")
+    ap.add_argument("--events", type=int, default=1_000_000, help="camera events per step")
+    ap.add_argument("--schedule", type=str, default="", help="pix_per_lane,waves_per_wg,wg_per_cu")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-graph", action="store_true", help="eager launches instead of graph replay")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import dl0sim.workloads as W
+    import paper_1307_6489_amd as rta
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    pool = W.c1_pool(args.pool, seed=1)
+    idx, ty, off = W.stream_order(pool, args.events, seed=3)
+    log("pool: %d events, %.2f GB, generated in %.1f s" % (pool.n, pool.blob.nbytes / 1e9, time.time() - t0))
+
+    cams = [rta.Camera.from_type(c) for c in pool.cams]
+    pipe = rta.Pipeline(cams, do_stereo=False)
+    if args.schedule:
+        pipe.set_schedule(*[int(v) for v in args.schedule.split(",")])
+    blob_d = torch.from_numpy(pool.blob).to(dev)
+    ty_d = torch.from_numpy(ty).to(dev)
+    off_d = torch.from_numpy(off).to(dev)
+    b = pipe.make_batch(blob_d, ty_d, off_d)
+    tel, _ = pipe.alloc_outputs(b, dev)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+
+    with torch.cuda.stream(stream):
+        graph = None if args.no_graph else pipe.capture(b, tel)
+
+        def step():
+            if graph is not None:
+                graph.launch(stream)
+            else:
+                pipe.process(b, tel, stream=stream)
+
+        for _ in range(args.warmup):
+            step()
+        stream.synchronize()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            ev[s][0].record(stream)
+            step()
+            ev[s][1].record(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    status = pipe.status()
+    if status:
+        raise RuntimeError("device status word %#x" % status)
+
+    wall = t1 - t0
+    ms_step = wall / args.steps * 1e3
+    kern_ms = float(np.mean([a.elapsed_time(bb) for a, bb in ev]))
+    n = args.events
+    rec = rta.records(tel)
+    per_hg = np.array([c.n_pix * c.n_samp * 2 for c in pool.cams], np.int64)
+    samp = np.array([c.n_samp for c in pool.cams], np.int64)
+    dl0 = np.array([c.dl0_bytes for c in pool.cams], np.int64)
+    alg_bytes = int(per_hg[ty].sum() + (rec["n_lowgain"].astype(np.int64) * samp[ty] * 2).sum() + n * (64 + 12))
+    dl0_bytes = int(dl0[ty].sum())
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    out = {
+        "metric": "camera-events/s & input GB/s (calib+clean+Hillas), % of HBM peak",
+        "value": n / (ms_step * 1e-3),
+        "unit": "camera-events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16/i32/f32",
+        "data": "synthetic",
+        "input_GBps": dl0_bytes / (ms_step * 1e-3) / 1e9,
+        "hbm_frac_algorithmic": achieved / HBM_PEAK_GBPS,
+        "config": {
+            "workload": "dual-gain camera events, 1855x40 : 1764x25 : 2048x128 = 1:3:6, "
+                        "%d per step through a device-resident pool of %d unique events (%.2f GB), "
+                        "fused calibrate->clean->Hillas, graph replay" % (n, pool.n, pool.blob.nbytes / 1e9),
+            "camera_events_per_step": n,
+            "pool_events": pool.n,
+            "schedule": list(pipe.schedule()),
+            "graph": graph is not None,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_fused",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": None,
+            "alg_bytes_per_launch": alg_bytes,
+            "kernel_ms": kern_ms,
+        },
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(pool, ty, off)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,242 @@
+/*
+ * rta.h — C ABI of the MI355X low-level reconstruction library (librta.so).
+ *
+ * The real-time analysis reconstructs every camera event of the DL0 stream
+ * built by the Central Event Builder, event by event (paper, Sections 4.1 and
+ * 4.2): it calibrates the raw waveforms and produces the per-telescope image
+ * parameters from which gamma/hadron separation, energy and direction are
+ * derived.  The paper names these products but gives no formulas; the
+ * operations below implement the following definitions.
+ *
+ *   Gain selection   a pixel uses its low-gain trace iff its highest raw
+ *                    high-gain sample is >= hg_switch_adc (dual-gain only).
+ *   Extraction       W(s) = sum_{k<w} x[s+k] on the selected gain,
+ *                    s* = the earliest maximiser over s in [0, T-w],
+ *                    S = W(s*); peak = s* + earliest argmax of x[s*..s*+w-1].
+ *   Calibration      P = nearest-even(256 * ped) (Q8 fixed point),
+ *                    D = 256*S - w*P,  q = D / (256 * adc_per_pe)  [p.e.],
+ *                    Nt = sum_{k<w} k*(256*x[s*+k] - P),
+ *                    t = s* + Nt/D for D > 0, else s* + (w-1)/2  [samples].
+ *   Cleaning         thresholds Tx = ceil(256 * adc_per_pe * level) (exact);
+ *                    mask_i = (D_i >= Tb_i and a neighbour has D_j >= Tp_j)
+ *                          or (D_i >= Tp_i and a neighbour has D_j >= Tb_j),
+ *                    every threshold taken at that pixel's selected gain.
+ *   Hillas           charge-weighted, centred moments over the mask: size,
+ *                    centre of gravity, length = sqrt(l+), width =
+ *                    sqrt(l-) with l+ >= l- the eigenvalues of the charge-
+ *                    weighted covariance (l- taken as the second moment
+ *                    about the major axis), psi in (-pi/2, pi/2],
+ *                    skewness / kurtosis of the longitudinal coordinate
+ *                    l = (x - cog_x) cos psi + (y - cog_y) sin psi, the
+ *                    unweighted least-squares slope / intercept of t over l,
+ *                    leakage (charge fraction on pixels with < 6 neighbours),
+ *                    number of islands (connected components of the mask).
+ *                    Fewer than two mask pixels: the invalid flag is set and
+ *                    every float field except size is NaN.
+ *   Stereo           point p of the nominal frame (camera metres / focal
+ *                    length) minimising sum_i w_i (n_i . (p - cog_i/f_i))^2,
+ *                    n_i = (-sin psi_i, cos psi_i), w_i = size (1 - width /
+ *                    length); telescopes with invalid Hillas or width/length
+ *                    > max_width_ratio are dropped; fewer than two, or a
+ *                    normal matrix with condition number >= max_cond, give
+ *                    NaN and the invalid flag.
+ *
+ * Trace layout (one camera event, uint16): [G][T][Npad] — gain, then sample,
+ * then pixel, with Npad = round_up(N, 8) (pad pixels are ignored).  One event
+ * occupies G*T*Npad elements; its first element must be 16-byte aligned.
+ *
+ * Conventions.  Pointers named in a stage call are DEVICE pointers owned by
+ * the caller unless stated otherwise; the library never frees them and never
+ * allocates on their behalf.  Every stage call is asynchronous on the given
+ * HIP stream (NULL = the null stream) and never synchronises it; host-side
+ * argument checks run before anything is launched and return an error code
+ * without launching.  Data errors found inside kernels (a bad descriptor) set
+ * bits in the pipeline's device status word and the record's flags; kernels
+ * never trap.  Handles are immutable after creation and may be shared by
+ * threads; calls that reuse a pipeline's work queue (rta_process_batch, its
+ * graphs) must not overlap on different streams.
+ */
+#ifndef RTA_H
+#define RTA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RTA_VERSION 1
+#define RTA_MAX_PIX 2048      /* largest camera (pixels) */
+#define RTA_MAX_SAMP 255      /* largest trace length */
+#define RTA_MAX_TYPES 8       /* camera types per pipeline */
+
+typedef enum rta_status {
+  RTA_OK = 0,
+  RTA_E_INVALID_ARG = 1,  /* null handle/pointer, negative count, misalignment */
+  RTA_E_SHAPE = 2,        /* unsupported size: N > RTA_MAX_PIX, T > RTA_MAX_SAMP, window not compiled */
+  RTA_E_HIP = 3,          /* a HIP runtime call failed (message in rta_last_error) */
+  RTA_E_NOMEM = 4,        /* device or host allocation for a handle failed */
+  RTA_E_UNSUPPORTED = 5   /* schedule or option not available */
+} rta_status;
+
+/* record flag bits (rta_hillas_rec.flags) */
+#define RTA_FLAG_HILLAS_INVALID 0x1u  /* fewer than two mask pixels */
+#define RTA_FLAG_TIME_INVALID 0x2u    /* time gradient undefined (all l equal) */
+#define RTA_FLAG_LOW_GAIN 0x4u        /* at least one pixel used its low gain */
+#define RTA_FLAG_BAD_DESCRIPTOR 0x8u  /* telescope descriptor rejected in-kernel */
+#define RTA_FLAG_MLP_FALLBACK 0x10u   /* box cuts used instead of the network */
+/* event flag bits (rta_event_rec.flags) */
+#define RTA_EVT_STEREO_INVALID 0x1u
+#define RTA_EVT_NO_MLP 0x2u
+/* device status word bits (rta_batch_status) */
+#define RTA_STATUS_BAD_TYPE 0x1u
+#define RTA_STATUS_BAD_OFFSET 0x2u
+#define RTA_STATUS_BAD_EVENT 0x4u
+
+typedef void* rta_stream; /* hipStream_t */
+
+typedef struct rta_camera rta_camera;
+typedef struct rta_pipeline rta_pipeline;
+typedef struct rta_graph rta_graph;
+typedef struct rta_mlp rta_mlp;
+
+/* Camera type description.  All pointers are HOST memory, read during
+ * rta_camera_create only (copied to device tables). */
+typedef struct rta_camera_desc {
+  int32_t n_pix;          /* N, 1..RTA_MAX_PIX */
+  int32_t n_samp;         /* T, window..RTA_MAX_SAMP */
+  int32_t n_gain;         /* 1 or 2 (0 = high, 1 = low gain) */
+  int32_t window;         /* w, compiled set: 4 */
+  int32_t hg_switch_adc;  /* low gain iff max raw high-gain sample >= this */
+  int32_t max_nbr;        /* columns of nbr, <= 6 */
+  const float* pix_x;     /* [N] metres */
+  const float* pix_y;     /* [N] metres */
+  const int32_t* nbr;     /* [N][max_nbr] neighbour pixel indices, -1 padded */
+  const float* ped;       /* [G][N] pedestal per sample, ADC */
+  const float* adc_per_pe;/* [G][N] ADC counts per photo-electron, > 0 */
+  float focal_m;          /* focal length (stereo nominal frame) */
+  float t_pic;            /* picture level, p.e. */
+  float t_bnd;            /* boundary level, p.e., <= t_pic */
+} rta_camera_desc;
+
+typedef struct rta_camera_info {
+  int32_t n_pix, n_pix_pad, n_samp, n_gain, window, pad_;
+  int64_t event_elems;    /* uint16 elements per camera event: G*T*Npad */
+} rta_camera_info;
+
+/* Per-telescope image record, 64 bytes. */
+typedef struct rta_hillas_rec {
+  float size, cog_x, cog_y, length, width, psi, skewness, kurtosis;
+  float time_gradient, time_intercept, leakage, cog_dist;
+  int32_t n_pix, n_islands, n_lowgain;
+  uint32_t flags;
+} rta_hillas_rec;
+
+/* Per-array-event record, 32 bytes. */
+typedef struct rta_event_rec {
+  float dir_x, dir_y;     /* nominal frame, radians */
+  float cond;             /* condition number of the stereo normal matrix */
+  float gammaness;        /* size-weighted mean gamma score (NaN without a network) */
+  float log10_energy;     /* size-weighted mean log10(E / TeV) */
+  int32_t n_tel, n_used;
+  uint32_t flags;
+} rta_event_rec;
+
+/* A ragged batch of array events.  Every pointer is DEVICE memory. */
+typedef struct rta_batch {
+  const uint16_t* traces;       /* trace pool base (16-byte aligned) */
+  int64_t traces_len;           /* pool length in uint16 elements */
+  const int64_t* evt_tel_off;   /* [n_evt + 1] telescopes of event e: [off[e], off[e+1]) */
+  const int32_t* tel_type;      /* [n_tel] index into the pipeline's camera list */
+  const int64_t* tel_trace_off; /* [n_tel] element offset of the telescope's trace block (multiple of 8) */
+  int64_t n_evt;
+  int64_t n_tel;
+} rta_batch;
+
+typedef struct rta_pipeline_params {
+  int32_t do_stereo;        /* 1: per-event stereo + event records */
+  int32_t pad_;
+  float max_width_ratio;    /* stereo: drop images with width/length above (0.9) */
+  float max_cond;           /* stereo: invalid at condition number >= this (1e4) */
+} rta_pipeline_params;
+
+/* Launch schedule of the fused kernel (chosen by the autotuner). */
+typedef struct rta_schedule {
+  int32_t pix_per_lane;     /* 2, 4 or 8 pixels per lane (4-, 8- or 16-byte slice loads) */
+  int32_t waves_per_wg;     /* 4 or 8 (256 or 512 threads) */
+  int32_t wg_per_cu;        /* persistent workgroups per compute unit, 1..4 */
+  int32_t pad_;
+} rta_schedule;
+
+const char* rta_status_str(rta_status s);
+/* Message of the last failing call on this host thread ("" if none). */
+const char* rta_last_error(void);
+int32_t rta_version(void);
+/* Number of compute units of the current device (for schedules). */
+rta_status rta_device_cus(int32_t* n_cu);
+
+/* Create / destroy a camera type.  Quantises pedestals to Q8 and builds the
+ * integer cleaning thresholds and neighbour tables on the current device. */
+rta_status rta_camera_create(const rta_camera_desc* desc, rta_camera** out);
+rta_status rta_camera_destroy(rta_camera* cam);
+rta_status rta_camera_get_info(const rta_camera* cam, rta_camera_info* info);
+
+/* Calibration + extraction of n_evt camera events of one type.
+ * traces: [n_evt][G][T][Npad].  Outputs [n_evt][N], each NULLABLE:
+ * S, D (int32), sstar, peak, gain (uint8), q (p.e.), t (samples) as float. */
+rta_status rta_calibrate(const rta_camera* cam, const uint16_t* traces, int64_t n_evt, int32_t* S, int32_t* D,
+                         uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q, float* t, rta_stream stream);
+
+/* Two-level tailcut of n_evt events.  D, gain: [n_evt][N] (gain NULLABLE =
+ * all high gain).  mask: [n_evt][N] 0/1. */
+rta_status rta_clean(const rta_camera* cam, const int32_t* D, const uint8_t* gain, int64_t n_evt, uint8_t* mask,
+                     rta_stream stream);
+
+/* Hillas parameters of n_evt events from calibrated charges (D in Q8 units
+ * and its gain, NULLABLE = all high gain), times t and the mask, all
+ * [n_evt][N].  out: [n_evt] records. */
+rta_status rta_hillas(const rta_camera* cam, const int32_t* D, const uint8_t* gain, const float* t,
+                      const uint8_t* mask, int64_t n_evt, rta_hillas_rec* out, rta_stream stream);
+
+/* A pipeline over 1..RTA_MAX_TYPES camera types (the handles must outlive it). */
+rta_status rta_pipeline_create(rta_camera* const* cams, int32_t n_types, const rta_pipeline_params* params,
+                               rta_pipeline** out);
+rta_status rta_pipeline_destroy(rta_pipeline* pipe);
+rta_status rta_set_schedule(rta_pipeline* pipe, const rta_schedule* s);
+rta_status rta_get_schedule(const rta_pipeline* pipe, rta_schedule* s);
+/* All schedules compiled into the library; *n receives the count. */
+rta_status rta_list_schedules(rta_schedule* out, int32_t cap, int32_t* n);
+
+/* The fused path: one persistent kernel runs calibration -> cleaning ->
+ * Hillas for every telescope of the batch (dynamic work queue), then (if
+ * do_stereo) one pass per array event computes stereo, network scores and
+ * the event record.  tel_out: [n_tel]; evt_out: [n_evt] (NULLABLE when
+ * do_stereo == 0). */
+rta_status rta_process_batch(rta_pipeline* pipe, const rta_batch* batch, rta_hillas_rec* tel_out,
+                             rta_event_rec* evt_out, rta_stream stream);
+
+/* Stereo per array event from existing telescope records, using the
+ * pipeline's focal lengths and cuts.  evt_tel_off [n_evt+1] (values in
+ * [0, n_tel]), tel_type [n_tel], tel [n_tel], evt_out [n_evt]. */
+rta_status rta_stereo(rta_pipeline* pipe, const int64_t* evt_tel_off, const int32_t* tel_type, int64_t n_evt,
+                      int64_t n_tel, const rta_hillas_rec* tel, rta_event_rec* evt_out, rta_stream stream);
+
+/* Synchronises the pipeline's status read: copies the device status word
+ * (RTA_STATUS_* bits accumulated since the last call) and clears it. */
+rta_status rta_batch_status(rta_pipeline* pipe, uint32_t* status);
+
+/* Capture rta_process_batch(pipe, batch, ...) with these exact pointers and
+ * sizes into a HIP graph (captured on a library-owned stream); replay it with
+ * rta_graph_launch on any stream.  The batch's device arrays may be rewritten
+ * between replays; their sizes may not. */
+rta_status rta_graph_capture(rta_pipeline* pipe, const rta_batch* batch, rta_hillas_rec* tel_out,
+                             rta_event_rec* evt_out, rta_graph** out);
+rta_status rta_graph_launch(rta_graph* g, rta_stream stream);
+rta_status rta_graph_destroy(rta_graph* g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTA_H */

@@ -1,0 +1,351 @@
+"""MI355X-native low-level reconstruction of the CTA real-time analysis.
+
+Thin Python binding over ``librta.so`` (C ABI declared in ``include/rta.h``).
+It only marshals arguments: every step of the reconstruction runs in the HIP
+kernels of the library.  PyTorch supplies device memory and streams.  If the
+library is missing or fails to load, every entry point raises; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librta.so")
+
+RTA_OK = 0
+STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "unsupported shape", 3: "HIP runtime error",
+                4: "out of memory", 5: "unsupported option"}
+FLAG_HILLAS_INVALID = 0x1
+FLAG_TIME_INVALID = 0x2
+FLAG_LOW_GAIN = 0x4
+FLAG_BAD_DESCRIPTOR = 0x8
+FLAG_MLP_FALLBACK = 0x10
+EVT_STEREO_INVALID = 0x1
+EVT_NO_MLP = 0x2
+STATUS_BAD_TYPE = 0x1
+STATUS_BAD_OFFSET = 0x2
+STATUS_BAD_EVENT = 0x4
+MAX_PIX = 2048
+MAX_SAMP = 255
+MAX_TYPES = 8
+
+
+class RTAError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(status, "?"), status, msg))
+        self.status = status
+
+
+class CameraDesc(ctypes.Structure):
+    _fields_ = [("n_pix", ctypes.c_int32), ("n_samp", ctypes.c_int32), ("n_gain", ctypes.c_int32),
+                ("window", ctypes.c_int32), ("hg_switch_adc", ctypes.c_int32), ("max_nbr", ctypes.c_int32),
+                ("pix_x", ctypes.c_void_p), ("pix_y", ctypes.c_void_p), ("nbr", ctypes.c_void_p),
+                ("ped", ctypes.c_void_p), ("adc_per_pe", ctypes.c_void_p), ("focal_m", ctypes.c_float),
+                ("t_pic", ctypes.c_float), ("t_bnd", ctypes.c_float)]
+
+
+class CameraInfo(ctypes.Structure):
+    _fields_ = [("n_pix", ctypes.c_int32), ("n_pix_pad", ctypes.c_int32), ("n_samp", ctypes.c_int32),
+                ("n_gain", ctypes.c_int32), ("window", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("event_elems", ctypes.c_int64)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("traces", ctypes.c_void_p), ("traces_len", ctypes.c_int64), ("evt_tel_off", ctypes.c_void_p),
+                ("tel_type", ctypes.c_void_p), ("tel_trace_off", ctypes.c_void_p), ("n_evt", ctypes.c_int64),
+                ("n_tel", ctypes.c_int64)]
+
+
+class PipelineParams(ctypes.Structure):
+    _fields_ = [("do_stereo", ctypes.c_int32), ("pad_", ctypes.c_int32), ("max_width_ratio", ctypes.c_float),
+                ("max_cond", ctypes.c_float)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("pix_per_lane", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.pix_per_lane, self.waves_per_wg, self.wg_per_cu)
+
+
+HILLAS_FIELDS = ("size", "cog_x", "cog_y", "length", "width", "psi", "skewness", "kurtosis",
+                 "time_gradient", "time_intercept", "leakage", "cog_dist")
+HILLAS_DTYPE = np.dtype([(f, "<f4") for f in HILLAS_FIELDS]
+                        + [("n_pix", "<i4"), ("n_islands", "<i4"), ("n_lowgain", "<i4"), ("flags", "<u4")])
+EVENT_DTYPE = np.dtype([("dir_x", "<f4"), ("dir_y", "<f4"), ("cond", "<f4"), ("gammaness", "<f4"),
+                        ("log10_energy", "<f4"), ("n_tel", "<i4"), ("n_used", "<i4"), ("flags", "<u4")])
+
+# C symbols declared in include/rta.h: name -> (argtypes, restype)
+_vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+SYMBOLS = {
+    "rta_status_str": ([ctypes.c_int], ctypes.c_char_p),
+    "rta_last_error": ([], ctypes.c_char_p),
+    "rta_version": ([], _i32),
+    "rta_device_cus": ([_vp], ctypes.c_int),
+    "rta_camera_create": ([_vp, _vp], ctypes.c_int),
+    "rta_camera_destroy": ([_vp], ctypes.c_int),
+    "rta_camera_get_info": ([_vp, _vp], ctypes.c_int),
+    "rta_calibrate": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "rta_clean": ([_vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
+    "rta_hillas": ([_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
+    "rta_pipeline_create": ([_vp, _i32, _vp, _vp], ctypes.c_int),
+    "rta_pipeline_destroy": ([_vp], ctypes.c_int),
+    "rta_set_schedule": ([_vp, _vp], ctypes.c_int),
+    "rta_get_schedule": ([_vp, _vp], ctypes.c_int),
+    "rta_list_schedules": ([_vp, _i32, _vp], ctypes.c_int),
+    "rta_process_batch": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "rta_stereo": ([_vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
+    "rta_batch_status": ([_vp, _vp], ctypes.c_int),
+    "rta_graph_capture": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "rta_graph_launch": ([_vp, _vp], ctypes.c_int),
+    "rta_graph_destroy": ([_vp], ctypes.c_int),
+}
+
+_lib = None
+
+
+def lib():
+    """Load librta.so; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librta.so is not built (run __graft_entry__.build() or "
+                               "python paper_1307_6489_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SYMBOLS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != RTA_OK:
+        raise RTAError(status, lib().rta_last_error().decode())
+
+
+def _ptr(t):
+    """Device (or host) address of a tensor / array, None for None."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return ctypes.c_void_p(t.data_ptr())
+    return t.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require(t, dtype, shape=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+
+
+def device_cus():
+    n = ctypes.c_int32()
+    _check(lib().rta_device_cus(ctypes.byref(n)))
+    return n.value
+
+
+def list_schedules():
+    n = ctypes.c_int32()
+    _check(lib().rta_list_schedules(None, 0, ctypes.byref(n)))
+    arr = (Schedule * n.value)()
+    _check(lib().rta_list_schedules(arr, n.value, ctypes.byref(n)))
+    return [s.as_tuple() for s in arr]
+
+
+class Camera:
+    """A camera type on the current device (pedestals in Q8, integer cleaning
+    thresholds, neighbour table)."""
+
+    def __init__(self, n_pix, n_samp, n_gain, x, y, nbr, ped, adc_per_pe, focal_m, window=4, hg_switch_adc=4000,
+                 t_pic=10.0, t_bnd=5.0):
+        self._keep = dict(x=np.ascontiguousarray(x, np.float32), y=np.ascontiguousarray(y, np.float32),
+                          nbr=np.ascontiguousarray(nbr, np.int32),
+                          ped=np.ascontiguousarray(ped, np.float32).reshape(n_gain, n_pix),
+                          a=np.ascontiguousarray(adc_per_pe, np.float32).reshape(n_gain, n_pix))
+        k = self._keep
+        d = CameraDesc(n_pix, n_samp, n_gain, window, hg_switch_adc, k["nbr"].shape[1] if k["nbr"].ndim == 2 else 0,
+                       _ptr(k["x"]), _ptr(k["y"]), _ptr(k["nbr"]), _ptr(k["ped"]), _ptr(k["a"]), focal_m, t_pic,
+                       t_bnd)
+        h = ctypes.c_void_p()
+        _check(lib().rta_camera_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        info = CameraInfo()
+        _check(lib().rta_camera_get_info(h, ctypes.byref(info)))
+        self.n_pix, self.n_pix_pad, self.n_samp = info.n_pix, info.n_pix_pad, info.n_samp
+        self.n_gain, self.window, self.event_elems = info.n_gain, info.window, info.event_elems
+        self.focal_m = focal_m
+
+    @classmethod
+    def from_type(cls, ct, t_pic=10.0, t_bnd=5.0):
+        """From any camera-type object with n_pix, n_samp, n_gain, geom.{x,y,nbr},
+        ped, adc_per_pe, focal_m, window and hg_switch_adc attributes."""
+        return cls(ct.n_pix, ct.n_samp, ct.n_gain, ct.geom.x, ct.geom.y, ct.geom.nbr, ct.ped, ct.adc_per_pe,
+                   ct.focal_m, ct.window, ct.hg_switch_adc, t_pic, t_bnd)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.rta_camera_destroy(h)
+            self.handle = None
+
+    def _n_evt(self, traces):
+        import torch
+        _require(traces, torch.uint16, name="traces")
+        if traces.numel() % self.event_elems:
+            raise ValueError("traces must hold whole events of %d elements" % self.event_elems)
+        return traces.numel() // self.event_elems
+
+
+def calibrate(cam: Camera, traces, stream=None, outputs=("S", "D", "sstar", "peak", "gain", "q", "t")):
+    """Per-pixel calibration of every event of ``traces`` (uint16 [E][G][T][Npad])."""
+    import torch
+    E = cam._n_evt(traces)
+    dev = traces.device
+    dt = {"S": torch.int32, "D": torch.int32, "sstar": torch.uint8, "peak": torch.uint8, "gain": torch.uint8,
+          "q": torch.float32, "t": torch.float32}
+    out = {k: torch.empty((E, cam.n_pix), dtype=dt[k], device=dev) for k in outputs}
+    g = lambda k: _ptr(out.get(k))  # noqa: E731
+    _check(lib().rta_calibrate(cam.handle, _ptr(traces), E, g("S"), g("D"), g("sstar"), g("peak"), g("gain"),
+                               g("q"), g("t"), _stream(stream)))
+    return out
+
+
+def clean(cam: Camera, D, gain=None, stream=None):
+    import torch
+    _require(D, torch.int32, name="D")
+    E = D.numel() // cam.n_pix
+    _require(D, torch.int32, (E, cam.n_pix), "D")
+    if gain is not None:
+        _require(gain, torch.uint8, (E, cam.n_pix), "gain")
+    mask = torch.empty((E, cam.n_pix), dtype=torch.uint8, device=D.device)
+    _check(lib().rta_clean(cam.handle, _ptr(D), _ptr(gain), E, _ptr(mask), _stream(stream)))
+    return mask
+
+
+def hillas(cam: Camera, D, gain, t, mask, stream=None):
+    import torch
+    E = D.numel() // cam.n_pix
+    _require(D, torch.int32, (E, cam.n_pix), "D")
+    _require(t, torch.float32, (E, cam.n_pix), "t")
+    _require(mask, torch.uint8, (E, cam.n_pix), "mask")
+    if gain is not None:
+        _require(gain, torch.uint8, (E, cam.n_pix), "gain")
+    out = torch.empty((E, 16), dtype=torch.float32, device=D.device)
+    _check(lib().rta_hillas(cam.handle, _ptr(D), _ptr(gain), _ptr(t), _ptr(mask), E, _ptr(out), _stream(stream)))
+    return out
+
+
+def records(t, dtype=HILLAS_DTYPE):
+    """Device record tensor ([n][16] or [n][8] float32) -> numpy structured array."""
+    a = t.detach().cpu().contiguous().numpy()
+    return a.view(dtype).reshape(-1)
+
+
+class Pipeline:
+    """Fused batched path over several camera types."""
+
+    def __init__(self, cams, do_stereo=True, max_width_ratio=0.9, max_cond=1e4):
+        self.cams = list(cams)
+        arr = (ctypes.c_void_p * len(self.cams))(*[c.handle.value for c in self.cams])
+        p = PipelineParams(1 if do_stereo else 0, 0, max_width_ratio, max_cond)
+        h = ctypes.c_void_p()
+        _check(lib().rta_pipeline_create(arr, len(self.cams), ctypes.byref(p), ctypes.byref(h)))
+        self.handle = h
+        self.do_stereo = do_stereo
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.rta_pipeline_destroy(h)
+            self.handle = None
+
+    def set_schedule(self, pix_per_lane, waves_per_wg, wg_per_cu):
+        s = Schedule(pix_per_lane, waves_per_wg, wg_per_cu, 0)
+        _check(lib().rta_set_schedule(self.handle, ctypes.byref(s)))
+
+    def schedule(self):
+        s = Schedule()
+        _check(lib().rta_get_schedule(self.handle, ctypes.byref(s)))
+        return s.as_tuple()
+
+    @staticmethod
+    def make_batch(traces, tel_type, tel_trace_off, evt_tel_off=None):
+        import torch
+        _require(traces, torch.uint16, name="traces")
+        _require(tel_type, torch.int32, name="tel_type")
+        _require(tel_trace_off, torch.int64, name="tel_trace_off")
+        n_tel = tel_type.numel()
+        if tel_trace_off.numel() != n_tel:
+            raise ValueError("tel_type and tel_trace_off differ in length")
+        n_evt = 0
+        if evt_tel_off is not None:
+            _require(evt_tel_off, torch.int64, name="evt_tel_off")
+            n_evt = evt_tel_off.numel() - 1
+        b = Batch(_ptr(traces), traces.numel(), _ptr(evt_tel_off), _ptr(tel_type), _ptr(tel_trace_off), n_evt, n_tel)
+        b._keep = (traces, tel_type, tel_trace_off, evt_tel_off)
+        return b
+
+    def alloc_outputs(self, batch, device):
+        import torch
+        tel = torch.empty((batch.n_tel, 16), dtype=torch.float32, device=device)
+        evt = torch.empty((max(batch.n_evt, 0), 8), dtype=torch.float32, device=device) if self.do_stereo else None
+        return tel, evt
+
+    def process(self, batch, tel_out, evt_out=None, stream=None):
+        _check(lib().rta_process_batch(self.handle, ctypes.byref(batch), _ptr(tel_out), _ptr(evt_out),
+                                       _stream(stream)))
+
+    def stereo(self, evt_tel_off, tel_type, tel_rec, stream=None):
+        import torch
+        n_evt = evt_tel_off.numel() - 1
+        out = torch.empty((n_evt, 8), dtype=torch.float32, device=tel_rec.device)
+        _check(lib().rta_stereo(self.handle, _ptr(evt_tel_off), _ptr(tel_type), n_evt, tel_type.numel(),
+                                _ptr(tel_rec), _ptr(out), _stream(stream)))
+        return out
+
+    def status(self):
+        s = ctypes.c_uint32()
+        _check(lib().rta_batch_status(self.handle, ctypes.byref(s)))
+        return s.value
+
+    def capture(self, batch, tel_out, evt_out=None):
+        return Graph(self, batch, tel_out, evt_out)
+
+
+class Graph:
+    """A captured rta_process_batch (fixed pointers and sizes)."""
+
+    def __init__(self, pipe, batch, tel_out, evt_out):
+        h = ctypes.c_void_p()
+        _check(lib().rta_graph_capture(pipe.handle, ctypes.byref(batch), _ptr(tel_out), _ptr(evt_out),
+                                       ctypes.byref(h)))
+        self.handle = h
+        self._keep = (pipe, batch, tel_out, evt_out)
+
+    def launch(self, stream=None):
+        _check(lib().rta_graph_launch(self.handle, _stream(stream)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.rta_graph_destroy(h)
+            self.handle = None

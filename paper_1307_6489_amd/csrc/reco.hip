@@ -1,0 +1,840 @@
+// HIP kernels of the low-level reconstruction for gfx950 (CDNA4).
+//
+// Calibration / signal extraction, two-level tailcut cleaning, islands and
+// Hillas moments of camera events (the calibration and image-parameter stage
+// of the real-time reconstruction, Sections 4.1-4.2 of the paper), plus the
+// per-array-event stereo direction.  The operations are defined in rta.h.
+//
+// Data flow of one camera event inside a workgroup:
+//   1. extraction   each lane owns PPL consecutive pixels and streams their
+//                   samples slice by slice (one PPL*2-byte load per slice, a
+//                   wavefront reads 64*PPL*2 contiguous bytes).  A running
+//                   w-sample window sum lives in registers; the argmax is a
+//                   single unsigned max of (W << 8 | 255 - s).  Dual-gain
+//                   cameras track the raw high-gain maximum with packed
+//                   16-bit max and re-stream the low gain only for lanes that
+//                   own a switched pixel.  D and the threshold flags go to LDS.
+//   2. mask         neighbour flags gathered from LDS, one ballot per
+//                   64-pixel word.
+//   3. compaction   popcount prefix over the mask words gives every cleaned
+//                   pixel a slot; q, x, y and the peak time (window samples
+//                   re-read for cleaned pixels only) are stored per slot.
+//   4. islands      lock-free union-find over the slots in LDS.
+//   5. Hillas       four block reductions (cog, centred second moments,
+//                   longitudinal moments + time sums, time-gradient sums),
+//                   each a fixed-order wavefront butterfly + wave-ordered sum,
+//                   so results are deterministic.
+#include <cfloat>
+#include <cmath>
+
+#include "rta_internal.h"
+
+namespace rta {
+namespace {
+
+constexpr int kWave = 64;
+constexpr float kNaN = __builtin_nanf("");
+
+__device__ __forceinline__ uint32_t lo16(uint32_t d) { return d & 0xffffu; }
+__device__ __forceinline__ uint32_t hi16(uint32_t d) { return d >> 16; }
+
+typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+
+// Per-halfword unsigned maximum of two packed pairs of uint16.
+__device__ __forceinline__ uint32_t pkmax16(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t,
+                            __builtin_elementwise_max(__builtin_bit_cast(us2, a), __builtin_bit_cast(us2, b)));
+}
+
+template <int ND>
+__device__ __forceinline__ void load_slice(uint32_t (&d)[ND], const uint16_t* p) {
+  if constexpr (ND == 4) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+  } else if constexpr (ND == 2) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    d[0] = v.x; d[1] = v.y;
+  } else {
+    d[0] = *reinterpret_cast<const uint32_t*>(p);
+  }
+}
+
+template <int PPL>
+__device__ __forceinline__ void load_i32(int32_t (&v)[PPL], const int32_t* p) {
+  if constexpr (PPL == 8) {
+    const int4 a = *reinterpret_cast<const int4*>(p);
+    const int4 b = *reinterpret_cast<const int4*>(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else if constexpr (PPL == 4) {
+    const int4 a = *reinterpret_cast<const int4*>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  } else {
+    const int2 a = *reinterpret_cast<const int2*>(p);
+    v[0] = a.x; v[1] = a.y;
+  }
+}
+
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uniform_i64(long long v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(unsigned long long)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// ---------------------------------------------------------------------------
+// Sliding-window argmax over one pixel group.
+// p0 points at sample 0 of the group's first pixel; sample k of the group is
+// the PPL*2 bytes at p0 + k*np.  On return key[p] = max over starts s of
+// (W(s) << 8) | (255 - s): the largest window sum, ties to the smallest s.
+// With TRACK_MAX, rmax holds the packed per-pixel raw maximum over all T.
+// ---------------------------------------------------------------------------
+template <int PPL, int W, bool TRACK_MAX>
+__device__ __forceinline__ void window_argmax(const uint16_t* __restrict__ p0, int np, int T, uint32_t (&key)[PPL],
+                                              uint32_t (&rmax)[PPL / 2]) {
+  constexpr int ND = PPL / 2;
+  constexpr int CH = 2 * W;  // samples per unrolled chunk; multiple of W keeps ring indices static
+  uint32_t hist[W][ND];
+  uint32_t ws[PPL];
+#pragma unroll
+  for (int k = 0; k < W; ++k) load_slice<ND>(hist[k], p0 + (size_t)k * np);
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) ws[p] = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+#pragma unroll
+    for (int h = 0; h < ND; ++h) {
+      ws[2 * h] += lo16(hist[k][h]);
+      ws[2 * h + 1] += hi16(hist[k][h]);
+      if constexpr (TRACK_MAX) rmax[h] = pkmax16(rmax[h], hist[k][h]);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) key[p] = (ws[p] << 8) | 255u;
+
+  // New sample k enters, sample k - W leaves; both share ring slot k % W.
+  int k0 = W;
+  for (; k0 + CH <= T; k0 += CH) {
+    uint32_t cur[CH][ND];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) load_slice<ND>(cur[j], p0 + (size_t)(k0 + j) * np);
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const uint32_t sc = 255u - (uint32_t)(k0 + j - W + 1);
+#pragma unroll
+      for (int h = 0; h < ND; ++h) {
+        const uint32_t nw = cur[j][h], od = hist[j % W][h];
+        ws[2 * h] += lo16(nw) - lo16(od);
+        ws[2 * h + 1] += hi16(nw) - hi16(od);
+        key[2 * h] = max(key[2 * h], (ws[2 * h] << 8) | sc);
+        key[2 * h + 1] = max(key[2 * h + 1], (ws[2 * h + 1] << 8) | sc);
+        if constexpr (TRACK_MAX) rmax[h] = pkmax16(rmax[h], nw);
+        hist[j % W][h] = nw;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+    if (k0 + j < T) {
+      uint32_t cur[ND];
+      load_slice<ND>(cur, p0 + (size_t)(k0 + j) * np);
+      const uint32_t sc = 255u - (uint32_t)(k0 + j - W + 1);
+#pragma unroll
+      for (int h = 0; h < ND; ++h) {
+        const uint32_t nw = cur[h], od = hist[j % W][h];
+        ws[2 * h] += lo16(nw) - lo16(od);
+        ws[2 * h + 1] += hi16(nw) - hi16(od);
+        key[2 * h] = max(key[2 * h], (ws[2 * h] << 8) | sc);
+        key[2 * h + 1] = max(key[2 * h + 1], (ws[2 * h + 1] << 8) | sc);
+        if constexpr (TRACK_MAX) rmax[h] = pkmax16(rmax[h], nw);
+        hist[j % W][h] = nw;
+      }
+    }
+  }
+}
+
+// Extraction of one pixel group on its selected gain.  Returns the bit mask
+// of pixels that switched to low gain.
+template <int PPL, int W>
+__device__ __forceinline__ uint32_t extract_group(const DevCam& c, const uint16_t* __restrict__ ev, int pix0, int np,
+                                                  int T, bool dual, uint32_t (&key)[PPL]) {
+  uint32_t rmax[PPL / 2];
+#pragma unroll
+  for (int h = 0; h < PPL / 2; ++h) rmax[h] = 0;
+  uint32_t sw = 0;
+  if (dual) {
+    window_argmax<PPL, W, true>(ev + pix0, np, T, key, rmax);
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const uint32_t m = (p & 1) ? hi16(rmax[p >> 1]) : lo16(rmax[p >> 1]);
+      if ((int)m >= c.hg_switch) sw |= 1u << p;
+    }
+    if (sw) {
+      uint32_t kl[PPL], unused[PPL / 2];
+      window_argmax<PPL, W, false>(ev + (size_t)T * np + pix0, np, T, kl, unused);
+#pragma unroll
+      for (int p = 0; p < PPL; ++p)
+        if ((sw >> p) & 1u) key[p] = kl[p];
+    }
+  } else {
+    window_argmax<PPL, W, false>(ev + pix0, np, T, key, rmax);
+  }
+  return sw;
+}
+
+// D = 256*S - w*P from the packed key.
+template <int W>
+__device__ __forceinline__ int32_t key_to_d(uint32_t key, int32_t P) {
+  return (int32_t)(key & 0xFFFFFF00u) - W * P;
+}
+
+// Time numerator Nt = sum_k k*(256*x[s+k] - P) and the in-window peak index
+// from the window samples (re-read from the trace).
+template <int W>
+__device__ __forceinline__ int32_t window_nt(const uint16_t* __restrict__ col, int np, int s, int32_t P, int* peak) {
+  int32_t nt = 0;
+  uint32_t pmax = col[(size_t)s * np];
+  int pk = s;
+#pragma unroll
+  for (int k = 1; k < W; ++k) {
+    const uint32_t x = col[(size_t)(s + k) * np];
+    nt += k * (256 * (int32_t)x - P);
+    if (x > pmax) { pmax = x; pk = s + k; }
+  }
+  if (peak) *peak = pk;
+  return nt;
+}
+
+// Peak time t = s* + Nt/D (window centre when D <= 0), evaluated in FP64.
+template <int W>
+__device__ __forceinline__ double peak_time(int s, int32_t nt, int32_t d) {
+  return d > 0 ? (double)s + (double)nt / (double)d : (double)s + 0.5 * (double)(W - 1);
+}
+
+__device__ __forceinline__ uint32_t pixel_flag(const DevCam& c, int g, int i, int32_t d) {
+  const int o = g * c.n_pix_pad + i;
+  return (uint32_t)(d >= c.thr_bnd[o]) | ((uint32_t)(d >= c.thr_pic[o]) << 1);
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup-shared state of one camera event.
+// ---------------------------------------------------------------------------
+struct TelSmem {
+  int32_t D[kMaxPix];        // calibrated charge (Q8); reused as union-find parents
+  uint16_t meta[kMaxPix];    // s* | gain << 8
+  uint8_t flag[kMaxPix];     // bit 0: D >= Tb, bit 1: D >= Tp
+  uint64_t mbits[kMaxWords]; // cleaning mask, one word per 64 pixels
+  int32_t wbase[kMaxWords + 1];
+  uint16_t list[kMaxPix];    // slot -> pixel
+  float q[kMaxPix];          // charge per slot, p.e.
+  double t[kMaxPix];         // peak time per slot, samples
+  double red[16 * 8];        // cross-wave reduction scratch
+};
+
+template <typename T, int NV, int NT>
+__device__ __forceinline__ void block_sum(T (&v)[NV], double* red_raw) {
+  T* red = reinterpret_cast<T*>(red_raw);
+  constexpr int NW = NT / kWave;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, kWave);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    T s = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += red[w * NV + k];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool mask_bit(const TelSmem& sm, int i) { return (sm.mbits[i >> 6] >> (i & 63)) & 1ull; }
+
+__device__ __forceinline__ int mask_slot(const TelSmem& sm, int i) {
+  const uint64_t w = sm.mbits[i >> 6];
+  return sm.wbase[i >> 6] + __popcll(w & ((1ull << (i & 63)) - 1ull));
+}
+
+// Phase 1 (fused): extraction of all pixels into LDS.  Returns this thread's
+// count of low-gain pixels.
+template <int PPL, int W, int NT>
+__device__ __forceinline__ int extract_phase(const DevCam& c, const uint16_t* __restrict__ ev, TelSmem& sm) {
+  const int N = c.n_pix, np = c.n_pix_pad, T = c.n_samp;
+  const bool dual = c.n_gain == 2;
+  int nlow = 0;
+  for (int pix0 = threadIdx.x * PPL; pix0 < N; pix0 += NT * PPL) {
+    uint32_t key[PPL];
+    const uint32_t sw = extract_group<PPL, W>(c, ev, pix0, np, T, dual, key);
+    int32_t P[PPL], Tb[PPL], Tp[PPL];
+    load_i32<PPL>(P, c.P256 + pix0);
+    load_i32<PPL>(Tb, c.thr_bnd + pix0);
+    load_i32<PPL>(Tp, c.thr_pic + pix0);
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const int i = pix0 + p;
+      if (i < N) {
+        const int g = (sw >> p) & 1u;
+        int32_t Pv = P[p], tb = Tb[p], tp = Tp[p];
+        if (g) { Pv = c.P256[np + i]; tb = c.thr_bnd[np + i]; tp = c.thr_pic[np + i]; }
+        const int32_t d = key_to_d<W>(key[p], Pv);
+        sm.D[i] = d;
+        sm.meta[i] = (uint16_t)((255u - (key[p] & 255u)) | ((uint32_t)g << 8));
+        sm.flag[i] = (uint8_t)((uint32_t)(d >= tb) | ((uint32_t)(d >= tp) << 1));
+        nlow += g;
+      }
+    }
+  }
+  return nlow;
+}
+
+// Phase 2: mask words from the flags (needs flags of all pixels).
+template <int NT>
+__device__ __forceinline__ void mask_phase(const DevCam& c, TelSmem& sm) {
+  const int N = c.n_pix, nw = (N + 63) >> 6;
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int base = threadIdx.x & ~(kWave - 1); base < nw * kWave; base += NT) {
+    const int i = base + lane;
+    bool m = false;
+    if (i < N) {
+      const uint32_t f = sm.flag[i];
+      if (f) {
+        const int4 nv = *reinterpret_cast<const int4*>(c.nbr + (size_t)i * kNbrCols);
+        const int16_t* nb = reinterpret_cast<const int16_t*>(&nv);
+        uint32_t any = 0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const int j = nb[k];
+          if (j >= 0) any |= sm.flag[j];
+        }
+        m = ((f & 1u) && (any & 2u)) || ((f & 2u) && (any & 1u));
+      }
+    }
+    const uint64_t b = __ballot(m);
+    if (lane == 0) sm.mbits[base >> 6] = b;
+  }
+}
+
+// Phase 3: exclusive prefix of the mask-word popcounts (one wavefront).
+__device__ __forceinline__ void scan_phase(int N, TelSmem& sm) {
+  const int nw = (N + 63) >> 6;
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    const int cnt = lane < nw ? __popcll(sm.mbits[lane]) : 0;
+    int inc = cnt;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int o = __shfl_up(inc, off, kWave);
+      if (lane >= off) inc += o;
+    }
+    if (lane < nw) sm.wbase[lane] = inc - cnt;
+    if (lane == nw - 1) sm.wbase[nw] = inc;
+  }
+}
+
+// Phase 4: slot list of cleaned pixels with q, x, y, t.  FUSED takes D /
+// gain / s* from LDS and re-reads the window samples for t; otherwise D,
+// gain and t come from global arrays of this event.
+template <int NT, int W, bool FUSED>
+__device__ __forceinline__ void list_phase(const DevCam& c, TelSmem& sm, const uint16_t* __restrict__ ev,
+                                           const int32_t* __restrict__ Dg, const uint8_t* __restrict__ gg,
+                                           const float* __restrict__ tg) {
+  const int N = c.n_pix, nw = (N + 63) >> 6, np = c.n_pix_pad;
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int base = threadIdx.x & ~(kWave - 1); base < nw * kWave; base += NT) {
+    const int i = base + lane;
+    const uint64_t bits = sm.mbits[base >> 6];
+    if ((bits >> lane) & 1ull) {
+      const int j = sm.wbase[base >> 6] + __popcll(bits & ((1ull << lane) - 1ull));
+      int32_t d;
+      int g;
+      double t;
+      if constexpr (FUSED) {
+        d = sm.D[i];
+        const uint32_t meta = sm.meta[i];
+        g = (int)(meta >> 8);
+        const int s = (int)(meta & 255u);
+        const int32_t nt = window_nt<W>(ev + (size_t)g * c.n_samp * np + i, np, s, c.P256[g * np + i], nullptr);
+        t = peak_time<W>(s, nt, d);
+      } else {
+        d = Dg[i];
+        g = gg ? (int)gg[i] : 0;
+        t = (double)tg[i];
+      }
+      sm.list[j] = (uint16_t)i;
+      sm.q[j] = (float)d / (256.0f * c.a[g * np + i]);
+      sm.t[j] = t;
+    }
+  }
+}
+
+__device__ __forceinline__ int uf_find(volatile int32_t* par, int x) {
+  int p = par[x];
+  while (p != x) {
+    x = p;
+    p = par[x];
+  }
+  return x;
+}
+
+// Hooks the larger root under the smaller; a root changes only by a CAS from
+// itself to a smaller index, so parents strictly decrease and find ends.
+__device__ __forceinline__ void uf_union(int32_t* par, int a, int b) {
+  volatile int32_t* vp = par;
+  for (;;) {
+    a = uf_find(vp, a);
+    b = uf_find(vp, b);
+    if (a == b) return;
+    if (a < b) { const int t = a; a = b; b = t; }
+    if (atomicCAS(&par[a], a, b) == a) return;
+  }
+}
+
+// Phase 5: islands = roots of the union-find forest over mask slots.
+// Returns this thread's root count.  sm.D is reused for the parents.
+template <int NT>
+__device__ __forceinline__ int islands_phase(const DevCam& c, TelSmem& sm, int n) {
+  int32_t* par = sm.D;
+  for (int j = threadIdx.x; j < n; j += NT) par[j] = j;
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += NT) {
+    const int i = sm.list[j];
+    const int4 nv = *reinterpret_cast<const int4*>(c.nbr + (size_t)i * kNbrCols);
+    const int16_t* nb = reinterpret_cast<const int16_t*>(&nv);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int m = nb[k];
+      if (m > i && mask_bit(sm, m)) uf_union(par, j, mask_slot(sm, m));
+    }
+  }
+  __syncthreads();
+  int roots = 0;
+  for (int j = threadIdx.x; j < n; j += NT) roots += (((volatile int32_t*)par)[j] == j);
+  return roots;
+}
+
+// Phase 6: Hillas reductions and the record.
+// Centre of gravity and second moments are FP32 sums of centred terms.  The
+// width comes from the minor-axis moment taken in the rotated frame (exact
+// for collinear pixels, unlike sqrt(det / l+), which keeps only half the
+// digits when the width is small).  The time regression (sums of l and t,
+// their centred cross products) is accumulated in FP64: times are absolute
+// sample numbers, so FP32 would cancel most digits of small time gradients.
+template <int NT>
+__device__ __forceinline__ void hillas_phase(const DevCam& c, TelSmem& sm, int n, int roots, int nlow,
+                                             rta_hillas_rec* out) {
+  float v1[6] = {0.f, 0.f, 0.f, 0.f, (float)roots, (float)nlow};
+  for (int j = threadIdx.x; j < n; j += NT) {
+    const int i = sm.list[j];
+    const float q = sm.q[j];
+    v1[0] += q;
+    v1[1] += q * c.x[i];
+    v1[2] += q * c.y[i];
+    if (c.border[i]) v1[3] += q;
+  }
+  block_sum<float, 6, NT>(v1, sm.red);
+  const float S = v1[0];
+  rta_hillas_rec r;
+  r.size = S;
+  r.n_pix = n;
+  r.n_islands = (int32_t)v1[4];
+  r.n_lowgain = (int32_t)v1[5];
+  r.flags = r.n_lowgain > 0 ? RTA_FLAG_LOW_GAIN : 0u;
+  if (n < 2 || !(S > 0.f)) {
+    r.cog_x = r.cog_y = r.length = r.width = r.psi = r.skewness = r.kurtosis = kNaN;
+    r.time_gradient = r.time_intercept = r.leakage = r.cog_dist = kNaN;
+    r.flags |= RTA_FLAG_HILLAS_INVALID | RTA_FLAG_TIME_INVALID;
+    if (threadIdx.x == 0) *out = r;
+    return;
+  }
+  const float xm = v1[1] / S, ym = v1[2] / S;
+  float v2[3] = {0.f, 0.f, 0.f};
+  for (int j = threadIdx.x; j < n; j += NT) {
+    const int i = sm.list[j];
+    const float q = sm.q[j], dx = c.x[i] - xm, dy = c.y[i] - ym;
+    v2[0] += q * dx * dx;
+    v2[1] += q * dy * dy;
+    v2[2] += q * dx * dy;
+  }
+  block_sum<float, 3, NT>(v2, sm.red);
+  const float sxx = v2[0] / S, syy = v2[1] / S, sxy = v2[2] / S;
+  const float hd = 0.5f * (sxx - syy);
+  const float lp = 0.5f * (sxx + syy) + sqrtf(hd * hd + sxy * sxy);
+  float psi = 0.5f * atan2f(2.0f * sxy, sxx - syy);
+  if (psi <= -0.5f * (float)M_PI) psi += (float)M_PI;
+  const float len = sqrtf(lp);
+  const float cs = cosf(psi), sn = sinf(psi);
+  double v3[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // q l^3, q l^4, q w^2, l, t
+  for (int j = threadIdx.x; j < n; j += NT) {
+    const int i = sm.list[j];
+    const float q = sm.q[j], dx = c.x[i] - xm, dy = c.y[i] - ym;
+    const float l = dx * cs + dy * sn;
+    const float w = dy * cs - dx * sn;
+    const float l2 = l * l;
+    v3[0] += (double)(q * l2 * l);
+    v3[1] += (double)(q * l2 * l2);
+    v3[2] += (double)(q * w * w);
+    v3[3] += (double)l;
+    v3[4] += sm.t[j];
+  }
+  block_sum<double, 5, NT>(v3, sm.red);
+  const double lbar = v3[3] / (double)n, tbar = v3[4] / (double)n;
+  double v4[2] = {0.0, 0.0};
+  for (int j = threadIdx.x; j < n; j += NT) {
+    const int i = sm.list[j];
+    const float dx = c.x[i] - xm, dy = c.y[i] - ym;
+    const double l = (double)(dx * cs + dy * sn) - lbar;
+    v4[0] += l * l;
+    v4[1] += l * (sm.t[j] - tbar);
+  }
+  block_sum<double, 2, NT>(v4, sm.red);
+  r.cog_x = xm;
+  r.cog_y = ym;
+  r.length = len;
+  r.width = sqrtf(fmaxf((float)v3[2] / S, 0.f));
+  r.psi = psi;
+  const float len3 = len * len * len;
+  r.skewness = (float)v3[0] / (S * len3);
+  r.kurtosis = (float)v3[1] / (S * len3 * len);
+  r.leakage = v1[3] / S;
+  r.cog_dist = sqrtf(xm * xm + ym * ym);
+  if (v4[0] > 0.0) {
+    const double g = v4[1] / v4[0];
+    r.time_gradient = (float)g;
+    r.time_intercept = (float)(tbar - g * lbar);
+  } else {
+    r.time_gradient = r.time_intercept = kNaN;
+    r.flags |= RTA_FLAG_TIME_INVALID;
+  }
+  if (threadIdx.x == 0) *out = r;
+}
+
+template <int PPL, int W, int NT>
+__device__ __forceinline__ void process_telescope(const DevCam& c, const uint16_t* __restrict__ ev, TelSmem& sm,
+                                                  rta_hillas_rec* out) {
+  const int nlow = extract_phase<PPL, W, NT>(c, ev, sm);
+  __syncthreads();
+  mask_phase<NT>(c, sm);
+  __syncthreads();
+  scan_phase(c.n_pix, sm);
+  __syncthreads();
+  const int n = sm.wbase[(c.n_pix + 63) >> 6];
+  list_phase<NT, W, true>(c, sm, ev, nullptr, nullptr, nullptr);
+  __syncthreads();
+  const int roots = islands_phase<NT>(c, sm, n);
+  hillas_phase<NT>(c, sm, n, roots, nlow, out);
+}
+
+__device__ __forceinline__ void bad_record(rta_hillas_rec* out) {
+  rta_hillas_rec r;
+  r.size = r.cog_x = r.cog_y = r.length = r.width = r.psi = r.skewness = r.kurtosis = kNaN;
+  r.time_gradient = r.time_intercept = r.leakage = r.cog_dist = kNaN;
+  r.n_pix = r.n_islands = r.n_lowgain = 0;
+  r.flags = RTA_FLAG_BAD_DESCRIPTOR | RTA_FLAG_HILLAS_INVALID | RTA_FLAG_TIME_INVALID;
+  *out = r;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// Unfused calibration: one workgroup per camera event, per-pixel results to HBM.
+template <int PPL, int W, int NT>
+__global__ __launch_bounds__(NT) void k_calibrate(DevCam c, const uint16_t* __restrict__ traces, int32_t* S,
+                                                  int32_t* D, uint8_t* sstar, uint8_t* peak, uint8_t* gain,
+                                                  float* q, float* t) {
+  const int64_t e = blockIdx.x;
+  const int N = c.n_pix, np = c.n_pix_pad, T = c.n_samp;
+  const uint16_t* ev = traces + e * c.event_elems;
+  const size_t ob = (size_t)e * N;
+  for (int pix0 = threadIdx.x * PPL; pix0 < N; pix0 += NT * PPL) {
+    uint32_t key[PPL];
+    const uint32_t sw = extract_group<PPL, W>(c, ev, pix0, np, T, c.n_gain == 2, key);
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const int i = pix0 + p;
+      if (i >= N) break;
+      const int g = (sw >> p) & 1u;
+      const int s = 255 - (int)(key[p] & 255u);
+      const int32_t P = c.P256[g * np + i];
+      const int32_t d = key_to_d<W>(key[p], P);
+      int pk;
+      const int32_t nt = window_nt<W>(ev + (size_t)g * T * np + i, np, s, P, &pk);
+      const float tv = (float)peak_time<W>(s, nt, d);
+      if (S) S[ob + i] = (int32_t)(key[p] >> 8);
+      if (D) D[ob + i] = d;
+      if (sstar) sstar[ob + i] = (uint8_t)s;
+      if (peak) peak[ob + i] = (uint8_t)pk;
+      if (gain) gain[ob + i] = (uint8_t)g;
+      if (q) q[ob + i] = (float)d / (256.0f * c.a[g * np + i]);
+      if (t) t[ob + i] = tv;
+    }
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_clean(DevCam c, const int32_t* __restrict__ D, const uint8_t* __restrict__ gain,
+                                              uint8_t* __restrict__ mask) {
+  __shared__ TelSmem sm;
+  const int64_t e = blockIdx.x;
+  const int N = c.n_pix;
+  const size_t ob = (size_t)e * N;
+  for (int i = threadIdx.x; i < N; i += NT) {
+    const int g = gain ? (int)gain[ob + i] : 0;
+    sm.flag[i] = (uint8_t)pixel_flag(c, g, i, D[ob + i]);
+  }
+  __syncthreads();
+  mask_phase<NT>(c, sm);
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += NT) mask[ob + i] = (uint8_t)mask_bit(sm, i);
+}
+
+template <int W, int NT>
+__global__ __launch_bounds__(NT) void k_hillas(DevCam c, const int32_t* __restrict__ D,
+                                               const uint8_t* __restrict__ gain, const float* __restrict__ t,
+                                               const uint8_t* __restrict__ mask, rta_hillas_rec* out) {
+  __shared__ TelSmem sm;
+  const int64_t e = blockIdx.x;
+  const int N = c.n_pix, nw = (N + 63) >> 6;
+  const size_t ob = (size_t)e * N;
+  const int lane = threadIdx.x & (kWave - 1);
+  int nlow = 0;
+  for (int base = threadIdx.x & ~(kWave - 1); base < nw * kWave; base += NT) {
+    const int i = base + lane;
+    const bool m = i < N && mask[ob + i] != 0;
+    if (i < N && gain) nlow += gain[ob + i] == 1;
+    const uint64_t b = __ballot(m);
+    if (lane == 0) sm.mbits[base >> 6] = b;
+  }
+  __syncthreads();
+  scan_phase(N, sm);
+  __syncthreads();
+  const int n = sm.wbase[nw];
+  list_phase<NT, W, false>(c, sm, nullptr, D + ob, gain ? gain + ob : nullptr, t + ob);
+  __syncthreads();
+  const int roots = islands_phase<NT>(c, sm, n);
+  hillas_phase<NT>(c, sm, n, roots, nlow, out + e);
+}
+
+__global__ void k_queue_reset(unsigned long long* q) {
+  if (threadIdx.x == 0) *q = 0ull;
+}
+
+// Fused persistent kernel: workgroups pull telescopes from a global counter
+// until the batch is drained; every telescope runs calibration -> cleaning ->
+// Hillas with all intermediates in LDS.
+template <int PPL, int W, int NT>
+__global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
+  __shared__ TelSmem sm;
+  __shared__ long long s_tel;
+  for (;;) {
+    if (threadIdx.x == 0) s_tel = (long long)atomicAdd(a.queue, 1ull);
+    __syncthreads();
+    const long long tel = uniform_i64(s_tel);
+    __syncthreads();
+    if (tel >= a.n_tel) return;
+    const int ty = uniform_i32(a.tel_type[tel]);
+    const long long off = uniform_i64(a.tel_trace_off[tel]);
+    if (ty < 0 || ty >= a.n_types) {
+      if (threadIdx.x == 0) {
+        bad_record(a.out + tel);
+        atomicOr(a.status, RTA_STATUS_BAD_TYPE);
+      }
+      continue;
+    }
+    const DevCam& c = a.cams[ty];
+    if (off < 0 || (off & 7) || off + c.event_elems > a.traces_len) {
+      if (threadIdx.x == 0) {
+        bad_record(a.out + tel);
+        atomicOr(a.status, RTA_STATUS_BAD_OFFSET);
+      }
+      continue;
+    }
+    process_telescope<PPL, W, NT>(c, a.traces + off, sm, a.out + tel);
+    __syncthreads();
+  }
+}
+
+// One wavefront per array event: stereo direction from the telescope records.
+constexpr int kEvtNT = 256;
+__global__ __launch_bounds__(kEvtNT) void k_event(EventArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t e = (int64_t)blockIdx.x * (kEvtNT / kWave) + (threadIdx.x / kWave);
+  if (e >= a.n_evt) return;
+  const int64_t lo = a.evt_tel_off[e], hi = a.evt_tel_off[e + 1];
+  rta_event_rec r;
+  r.gammaness = kNaN;
+  r.log10_energy = kNaN;
+  if (lo < 0 || hi < lo || hi > a.n_tel) {
+    if (lane == 0) {
+      r.dir_x = r.dir_y = r.cond = kNaN;
+      r.n_tel = 0;
+      r.n_used = 0;
+      r.flags = RTA_EVT_STEREO_INVALID | RTA_EVT_NO_MLP;
+      a.out[e] = r;
+      atomicOr(a.status, RTA_STATUS_BAD_EVENT);
+    }
+    return;
+  }
+  float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // A00, A01, A11, b0, b1, used
+  for (int64_t k = lo + lane; k < hi; k += kWave) {
+    const int ty = a.tel_type[k];
+    if (ty < 0 || ty >= a.n_types) continue;
+    const rta_hillas_rec h = a.tel[k];
+    if (h.flags & (RTA_FLAG_HILLAS_INVALID | RTA_FLAG_BAD_DESCRIPTOR)) continue;
+    if (!(h.length > 0.f) || !(h.width >= 0.f) || !isfinite(h.psi) || !isfinite(h.size)) continue;
+    const float ratio = h.width / h.length;
+    if (ratio > a.max_width_ratio) continue;
+    const float w = h.size * (1.0f - ratio);
+    const float f = a.focal[ty];
+    const float nx = -sinf(h.psi), ny = cosf(h.psi);
+    const float cx = h.cog_x / f, cy = h.cog_y / f;
+    const float nc = nx * cx + ny * cy;
+    v[0] += w * nx * nx;
+    v[1] += w * nx * ny;
+    v[2] += w * ny * ny;
+    v[3] += w * nc * nx;
+    v[4] += w * nc * ny;
+    v[5] += 1.f;
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, kWave);
+  }
+  if (lane == 0) {
+    const float A00 = v[0], A01 = v[1], A11 = v[2], b0 = v[3], b1 = v[4];
+    const float tr = A00 + A11, det = A00 * A11 - A01 * A01;
+    const float hd = 0.5f * (A00 - A11);
+    const float lmax = 0.5f * tr + sqrtf(hd * hd + A01 * A01);
+    const float lmin = lmax > 0.f ? det / lmax : 0.f;
+    const float cond = lmin > 0.f ? lmax / lmin : INFINITY;
+    r.cond = cond;
+    r.n_tel = (int32_t)(hi - lo);
+    r.n_used = (int32_t)v[5];
+    r.flags = RTA_EVT_NO_MLP;
+    if (r.n_used < 2 || !(cond < a.max_cond)) {
+      r.dir_x = r.dir_y = kNaN;
+      r.flags |= RTA_EVT_STEREO_INVALID;
+    } else {
+      r.dir_x = (A11 * b0 - A01 * b1) / det;
+      r.dir_y = (A00 * b1 - A01 * b0) / det;
+    }
+    a.out[e] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch tables
+// ---------------------------------------------------------------------------
+constexpr int kUnfusedNT = 256;
+constexpr int kUnfusedPPL = 4;
+
+template <int W>
+hipError_t launch_calibrate_w(const DevCam& c, const uint16_t* tr, int64_t n, int32_t* S, int32_t* D, uint8_t* ss,
+                              uint8_t* pk, uint8_t* g, float* q, float* t, hipStream_t st) {
+  hipLaunchKernelGGL((k_calibrate<kUnfusedPPL, W, kUnfusedNT>), dim3((unsigned)n), dim3(kUnfusedNT), 0, st, c, tr,
+                     S, D, ss, pk, g, q, t);
+  return hipGetLastError();
+}
+
+template <int W>
+hipError_t launch_hillas_w(const DevCam& c, const int32_t* D, const uint8_t* g, const float* t, const uint8_t* m,
+                           int64_t n, rta_hillas_rec* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_hillas<W, kUnfusedNT>), dim3((unsigned)n), dim3(kUnfusedNT), 0, st, c, D, g, t, m, out);
+  return hipGetLastError();
+}
+
+template <int PPL, int W, int NT>
+hipError_t launch_fused_t(const FusedArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_fused<PPL, W, NT>), dim3(grid), dim3(NT), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int W>
+hipError_t launch_fused_w(const FusedArgs& a, const rta_schedule& s, int grid, hipStream_t st) {
+  const int key = s.pix_per_lane * 100 + s.waves_per_wg;
+  switch (key) {
+    case 204: return launch_fused_t<2, W, 256>(a, grid, st);
+    case 208: return launch_fused_t<2, W, 512>(a, grid, st);
+    case 404: return launch_fused_t<4, W, 256>(a, grid, st);
+    case 408: return launch_fused_t<4, W, 512>(a, grid, st);
+    case 804: return launch_fused_t<8, W, 256>(a, grid, st);
+    case 808: return launch_fused_t<8, W, 512>(a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool window_supported(int w) { return w == 4; }
+
+bool schedule_supported(const rta_schedule& s) {
+  const bool ppl = s.pix_per_lane == 2 || s.pix_per_lane == 4 || s.pix_per_lane == 8;
+  const bool wv = s.waves_per_wg == 4 || s.waves_per_wg == 8;
+  return ppl && wv && s.wg_per_cu >= 1 && s.wg_per_cu <= 4;
+}
+
+int list_schedules(rta_schedule* out, int cap) {
+  int n = 0;
+  const int ppls[3] = {2, 4, 8}, waves[2] = {4, 8};
+  for (int p : ppls)
+    for (int w : waves)
+      for (int g = 1; g <= 4; ++g) {
+        if (out && n < cap) out[n] = rta_schedule{p, w, g, 0};
+        ++n;
+      }
+  return n;
+}
+
+hipError_t launch_calibrate(const DevCam& c, const uint16_t* traces, int64_t n_evt, int32_t* S, int32_t* D,
+                            uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q, float* t, hipStream_t st) {
+  switch (c.window) {
+    case 4: return launch_calibrate_w<4>(c, traces, n_evt, S, D, sstar, peak, gain, q, t, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_clean(const DevCam& c, const int32_t* D, const uint8_t* gain, int64_t n_evt, uint8_t* mask,
+                        hipStream_t st) {
+  hipLaunchKernelGGL((k_clean<kUnfusedNT>), dim3((unsigned)n_evt), dim3(kUnfusedNT), 0, st, c, D, gain, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_hillas(const DevCam& c, const int32_t* D, const uint8_t* gain, const float* t, const uint8_t* mask,
+                         int64_t n_evt, rta_hillas_rec* out, hipStream_t st) {
+  switch (c.window) {
+    case 4: return launch_hillas_w<4>(c, D, gain, t, mask, n_evt, out, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_queue_reset(unsigned long long* queue, hipStream_t st) {
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(const FusedArgs& a, const rta_schedule& s, int n_cu, hipStream_t st) {
+  long long grid = (long long)n_cu * s.wg_per_cu;
+  if (grid > a.n_tel) grid = a.n_tel;
+  if (grid < 1) grid = 1;
+  switch (a.window) {
+    case 4: return launch_fused_w<4>(a, s, (int)grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_event(const EventArgs& a, hipStream_t st) {
+  const int64_t per = kEvtNT / kWave;
+  const int64_t grid = (a.n_evt + per - 1) / per;
+  hipLaunchKernelGGL(k_event, dim3((unsigned)grid), dim3(kEvtNT), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace rta

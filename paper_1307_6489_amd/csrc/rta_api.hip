@@ -1,0 +1,432 @@
+// C ABI of librta: argument validation, camera tables, pipelines, graphs.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rta_internal.h"
+
+struct rta_camera {
+  rta::DevCam dev;
+  void* dmem = nullptr;
+  rta_camera_info info{};
+  int device = 0;
+};
+
+struct rta_pipeline {
+  std::vector<rta_camera*> cams;
+  rta_pipeline_params params{};
+  rta_schedule sched{};
+  int window = 0;
+  int n_cu = 0;
+  int device = 0;
+  unsigned long long* d_queue = nullptr;  // work-queue counter
+  uint32_t* d_status = nullptr;           // RTA_STATUS_* bits
+  hipStream_t capture_stream = nullptr;
+};
+
+struct rta_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+rta_status fail(rta_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define RTA_HIP(call)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail(RTA_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+size_t round256(size_t v) { return (v + 255) & ~size_t(255); }
+
+rta_status launch_batch(rta_pipeline* pipe, const rta_batch* b, rta_hillas_rec* tel_out, rta_event_rec* evt_out,
+                        hipStream_t st) {
+  rta::FusedArgs fa;
+  std::memset(&fa, 0, sizeof(fa));
+  for (size_t i = 0; i < pipe->cams.size(); ++i) fa.cams[i] = pipe->cams[i]->dev;
+  fa.n_types = (int32_t)pipe->cams.size();
+  fa.window = pipe->window;
+  fa.traces = b->traces;
+  fa.traces_len = b->traces_len;
+  fa.tel_type = b->tel_type;
+  fa.tel_trace_off = b->tel_trace_off;
+  fa.n_tel = b->n_tel;
+  fa.out = tel_out;
+  fa.queue = pipe->d_queue;
+  fa.status = pipe->d_status;
+  if (b->n_tel > 0) {
+    RTA_HIP(rta::launch_queue_reset(pipe->d_queue, st));
+    RTA_HIP(rta::launch_fused(fa, pipe->sched, pipe->n_cu, st));
+  }
+  if (pipe->params.do_stereo && b->n_evt > 0) {
+    rta::EventArgs ea;
+    std::memset(&ea, 0, sizeof(ea));
+    for (size_t i = 0; i < pipe->cams.size(); ++i) ea.focal[i] = pipe->cams[i]->dev.focal;
+    ea.n_types = (int32_t)pipe->cams.size();
+    ea.max_width_ratio = pipe->params.max_width_ratio;
+    ea.max_cond = pipe->params.max_cond;
+    ea.evt_tel_off = b->evt_tel_off;
+    ea.tel_type = b->tel_type;
+    ea.n_evt = b->n_evt;
+    ea.n_tel = b->n_tel;
+    ea.tel = tel_out;
+    ea.out = evt_out;
+    ea.status = pipe->d_status;
+    RTA_HIP(rta::launch_event(ea, st));
+  }
+  return RTA_OK;
+}
+
+rta_status check_batch(const rta_pipeline* pipe, const rta_batch* b, const rta_hillas_rec* tel_out,
+                       const rta_event_rec* evt_out) {
+  if (!pipe || !b) return fail(RTA_E_INVALID_ARG, "null pipeline or batch");
+  if (b->n_tel < 0 || b->n_evt < 0 || b->traces_len < 0) return fail(RTA_E_INVALID_ARG, "negative batch size");
+  if (b->n_tel > 0) {
+    if (!b->traces || !b->tel_type || !b->tel_trace_off || !tel_out)
+      return fail(RTA_E_INVALID_ARG, "null trace pool, descriptor or output pointer");
+    if (!aligned16(b->traces)) return fail(RTA_E_INVALID_ARG, "trace pool must be 16-byte aligned");
+  }
+  if (pipe->params.do_stereo && b->n_evt > 0) {
+    if (!b->evt_tel_off || !evt_out || !tel_out) return fail(RTA_E_INVALID_ARG, "null event offsets or output");
+    if ((int64_t)(b->n_evt + 3) / 4 > 0x7fffffffLL) return fail(RTA_E_SHAPE, "too many events for one launch");
+  }
+  return RTA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rta_status_str(rta_status s) {
+  switch (s) {
+    case RTA_OK: return "ok";
+    case RTA_E_INVALID_ARG: return "invalid argument";
+    case RTA_E_SHAPE: return "unsupported shape";
+    case RTA_E_HIP: return "HIP runtime error";
+    case RTA_E_NOMEM: return "out of memory";
+    case RTA_E_UNSUPPORTED: return "unsupported option";
+  }
+  return "unknown status";
+}
+
+const char* rta_last_error(void) { return g_err.c_str(); }
+
+int32_t rta_version(void) { return RTA_VERSION; }
+
+rta_status rta_device_cus(int32_t* n_cu) {
+  if (!n_cu) return fail(RTA_E_INVALID_ARG, "null n_cu");
+  int dev = 0, v = 0;
+  RTA_HIP(hipGetDevice(&dev));
+  RTA_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev));
+  *n_cu = v;
+  return RTA_OK;
+}
+
+rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
+  if (!d || !out) return fail(RTA_E_INVALID_ARG, "null descriptor or output handle");
+  *out = nullptr;
+  const int N = d->n_pix, T = d->n_samp, G = d->n_gain, w = d->window, M = d->max_nbr;
+  if (N < 1 || N > RTA_MAX_PIX) return fail(RTA_E_SHAPE, "n_pix must be in [1, RTA_MAX_PIX]");
+  if (G != 1 && G != 2) return fail(RTA_E_SHAPE, "n_gain must be 1 or 2");
+  if (!rta::window_supported(w)) return fail(RTA_E_SHAPE, "window not in the compiled set");
+  if (T < w || T > RTA_MAX_SAMP) return fail(RTA_E_SHAPE, "n_samp must be in [window, RTA_MAX_SAMP]");
+  if (M < 0 || M > 6) return fail(RTA_E_SHAPE, "max_nbr must be in [0, 6]");
+  if (!d->pix_x || !d->pix_y || !d->ped || !d->adc_per_pe || (M > 0 && !d->nbr))
+    return fail(RTA_E_INVALID_ARG, "null table pointer");
+  if (!std::isfinite(d->t_pic) || !std::isfinite(d->t_bnd) || d->t_bnd > d->t_pic)
+    return fail(RTA_E_INVALID_ARG, "cleaning levels must be finite with t_bnd <= t_pic");
+  if (!std::isfinite(d->focal_m) || !(d->focal_m > 0.f)) return fail(RTA_E_INVALID_ARG, "focal length must be > 0");
+  const int Np = (N + 7) & ~7;
+  std::vector<int32_t> P(G * Np, 0), Tp(G * Np, 0x7fffffff), Tb(G * Np, 0x7fffffff);
+  std::vector<float> A(G * Np, 1.f), X(Np, 0.f), Y(Np, 0.f);
+  std::vector<int16_t> nb(Np * rta::kNbrCols, -1);
+  std::vector<uint8_t> border(Np, 0);
+  for (int g = 0; g < G; ++g)
+    for (int i = 0; i < N; ++i) {
+      const float ped = d->ped[g * N + i], a = d->adc_per_pe[g * N + i];
+      if (!std::isfinite(ped) || std::fabs(ped) > 65536.f) return fail(RTA_E_INVALID_ARG, "pedestal out of range");
+      if (!std::isfinite(a) || !(a > 0.f)) return fail(RTA_E_INVALID_ARG, "adc_per_pe must be > 0");
+      // Q8 pedestal, nearest with ties to even (256 * ped is exact in double).
+      P[g * Np + i] = (int32_t)std::nearbyint(256.0 * (double)ped);
+      // 256 * a * level: a product of two floats is exact in double, so the
+      // ceiling is the exact integer threshold on D.
+      const double tp = std::ceil(256.0 * (double)a * (double)d->t_pic);
+      const double tb = std::ceil(256.0 * (double)a * (double)d->t_bnd);
+      if (std::fabs(tp) > 2.0e9 || std::fabs(tb) > 2.0e9) return fail(RTA_E_INVALID_ARG, "threshold overflow");
+      Tp[g * Np + i] = (int32_t)tp;
+      Tb[g * Np + i] = (int32_t)tb;
+      A[g * Np + i] = a;
+    }
+  for (int i = 0; i < N; ++i) {
+    X[i] = d->pix_x[i];
+    Y[i] = d->pix_y[i];
+    int cnt = 0;
+    for (int k = 0; k < M; ++k) {
+      const int j = d->nbr[(size_t)i * M + k];
+      if (j < -1 || j >= N || j == i) return fail(RTA_E_INVALID_ARG, "neighbour index out of range");
+      if (j >= 0) nb[(size_t)i * rta::kNbrCols + cnt++] = (int16_t)j;
+    }
+    border[i] = cnt < 6 ? 1 : 0;
+  }
+  // one device allocation, 256-byte aligned sub-arrays
+  const size_t oP = 0, oTp = oP + round256(P.size() * 4), oTb = oTp + round256(Tp.size() * 4);
+  const size_t oA = oTb + round256(Tb.size() * 4), oX = oA + round256(A.size() * 4);
+  const size_t oY = oX + round256(X.size() * 4), oN = oY + round256(Y.size() * 4);
+  const size_t oB = oN + round256(nb.size() * 2), total = oB + round256(border.size());
+  std::vector<uint8_t> host(total, 0);
+  std::memcpy(host.data() + oP, P.data(), P.size() * 4);
+  std::memcpy(host.data() + oTp, Tp.data(), Tp.size() * 4);
+  std::memcpy(host.data() + oTb, Tb.data(), Tb.size() * 4);
+  std::memcpy(host.data() + oA, A.data(), A.size() * 4);
+  std::memcpy(host.data() + oX, X.data(), X.size() * 4);
+  std::memcpy(host.data() + oY, Y.data(), Y.size() * 4);
+  std::memcpy(host.data() + oN, nb.data(), nb.size() * 2);
+  std::memcpy(host.data() + oB, border.data(), border.size());
+  rta_camera* cam = new (std::nothrow) rta_camera();
+  if (!cam) return fail(RTA_E_NOMEM, "host allocation failed");
+  if (hipGetDevice(&cam->device) != hipSuccess || hipMalloc(&cam->dmem, total) != hipSuccess) {
+    delete cam;
+    return fail(RTA_E_NOMEM, "device allocation for camera tables failed");
+  }
+  if (hipMemcpy(cam->dmem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(cam->dmem);
+    delete cam;
+    return fail(RTA_E_HIP, "copy of camera tables failed");
+  }
+  uint8_t* base = static_cast<uint8_t*>(cam->dmem);
+  rta::DevCam& c = cam->dev;
+  c.n_pix = N;
+  c.n_pix_pad = Np;
+  c.n_samp = T;
+  c.n_gain = G;
+  c.window = w;
+  c.hg_switch = d->hg_switch_adc;
+  c.event_elems = (int64_t)G * T * Np;
+  c.focal = d->focal_m;
+  c.pad_ = 0;
+  c.P256 = reinterpret_cast<const int32_t*>(base + oP);
+  c.thr_pic = reinterpret_cast<const int32_t*>(base + oTp);
+  c.thr_bnd = reinterpret_cast<const int32_t*>(base + oTb);
+  c.a = reinterpret_cast<const float*>(base + oA);
+  c.x = reinterpret_cast<const float*>(base + oX);
+  c.y = reinterpret_cast<const float*>(base + oY);
+  c.nbr = reinterpret_cast<const int16_t*>(base + oN);
+  c.border = base + oB;
+  cam->info = rta_camera_info{N, Np, T, G, w, 0, c.event_elems};
+  *out = cam;
+  return RTA_OK;
+}
+
+rta_status rta_camera_destroy(rta_camera* cam) {
+  if (!cam) return RTA_OK;
+  if (cam->dmem) (void)hipFree(cam->dmem);
+  delete cam;
+  return RTA_OK;
+}
+
+rta_status rta_camera_get_info(const rta_camera* cam, rta_camera_info* info) {
+  if (!cam || !info) return fail(RTA_E_INVALID_ARG, "null camera or info");
+  *info = cam->info;
+  return RTA_OK;
+}
+
+rta_status rta_calibrate(const rta_camera* cam, const uint16_t* traces, int64_t n_evt, int32_t* S, int32_t* D,
+                         uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q, float* t, rta_stream stream) {
+  if (!cam) return fail(RTA_E_INVALID_ARG, "null camera");
+  if (n_evt < 0) return fail(RTA_E_INVALID_ARG, "negative event count");
+  if (n_evt > 0x7fffffffLL) return fail(RTA_E_SHAPE, "too many events for one launch");
+  if (n_evt == 0) return RTA_OK;
+  if (!traces || !aligned16(traces)) return fail(RTA_E_INVALID_ARG, "traces must be non-null and 16-byte aligned");
+  RTA_HIP(rta::launch_calibrate(cam->dev, traces, n_evt, S, D, sstar, peak, gain, q, t, (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_clean(const rta_camera* cam, const int32_t* D, const uint8_t* gain, int64_t n_evt, uint8_t* mask,
+                     rta_stream stream) {
+  if (!cam) return fail(RTA_E_INVALID_ARG, "null camera");
+  if (n_evt < 0) return fail(RTA_E_INVALID_ARG, "negative event count");
+  if (n_evt > 0x7fffffffLL) return fail(RTA_E_SHAPE, "too many events for one launch");
+  if (n_evt == 0) return RTA_OK;
+  if (!D || !mask) return fail(RTA_E_INVALID_ARG, "null D or mask");
+  RTA_HIP(rta::launch_clean(cam->dev, D, gain, n_evt, mask, (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_hillas(const rta_camera* cam, const int32_t* D, const uint8_t* gain, const float* t,
+                      const uint8_t* mask, int64_t n_evt, rta_hillas_rec* out, rta_stream stream) {
+  if (!cam) return fail(RTA_E_INVALID_ARG, "null camera");
+  if (n_evt < 0) return fail(RTA_E_INVALID_ARG, "negative event count");
+  if (n_evt > 0x7fffffffLL) return fail(RTA_E_SHAPE, "too many events for one launch");
+  if (n_evt == 0) return RTA_OK;
+  if (!D || !t || !mask || !out) return fail(RTA_E_INVALID_ARG, "null D, t, mask or output");
+  RTA_HIP(rta::launch_hillas(cam->dev, D, gain, t, mask, n_evt, out, (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_pipeline_create(rta_camera* const* cams, int32_t n_types, const rta_pipeline_params* params,
+                               rta_pipeline** out) {
+  if (!out) return fail(RTA_E_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (!cams || !params || n_types < 1 || n_types > RTA_MAX_TYPES)
+    return fail(RTA_E_INVALID_ARG, "need 1..RTA_MAX_TYPES camera handles and params");
+  for (int i = 0; i < n_types; ++i)
+    if (!cams[i]) return fail(RTA_E_INVALID_ARG, "null camera handle");
+  for (int i = 1; i < n_types; ++i)
+    if (cams[i]->dev.window != cams[0]->dev.window) return fail(RTA_E_SHAPE, "all camera types need one window");
+  if (params->do_stereo && (!(params->max_width_ratio > 0.f) || !(params->max_cond > 1.f)))
+    return fail(RTA_E_INVALID_ARG, "stereo cuts must be positive");
+  rta_pipeline* p = new (std::nothrow) rta_pipeline();
+  if (!p) return fail(RTA_E_NOMEM, "host allocation failed");
+  p->cams.assign(cams, cams + n_types);
+  p->params = *params;
+  p->window = cams[0]->dev.window;
+  p->sched = rta_schedule{4, 8, 2, 0};
+  if (hipGetDevice(&p->device) != hipSuccess ||
+      hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) {
+    delete p;
+    return fail(RTA_E_HIP, "device query failed");
+  }
+  void* mem = nullptr;
+  if (hipMalloc(&mem, 256) != hipSuccess) {
+    delete p;
+    return fail(RTA_E_NOMEM, "device allocation failed");
+  }
+  p->d_queue = static_cast<unsigned long long*>(mem);
+  p->d_status = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(mem) + 64);
+  if (hipMemset(mem, 0, 256) != hipSuccess ||
+      hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipFree(mem);
+    delete p;
+    return fail(RTA_E_HIP, "pipeline initialisation failed");
+  }
+  *out = p;
+  return RTA_OK;
+}
+
+rta_status rta_pipeline_destroy(rta_pipeline* p) {
+  if (!p) return RTA_OK;
+  (void)hipDeviceSynchronize();
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+  if (p->d_queue) (void)hipFree(p->d_queue);
+  delete p;
+  return RTA_OK;
+}
+
+rta_status rta_set_schedule(rta_pipeline* p, const rta_schedule* s) {
+  if (!p || !s) return fail(RTA_E_INVALID_ARG, "null pipeline or schedule");
+  if (!rta::schedule_supported(*s)) return fail(RTA_E_UNSUPPORTED, "schedule not compiled");
+  p->sched = *s;
+  p->sched.pad_ = 0;
+  return RTA_OK;
+}
+
+rta_status rta_get_schedule(const rta_pipeline* p, rta_schedule* s) {
+  if (!p || !s) return fail(RTA_E_INVALID_ARG, "null pipeline or schedule");
+  *s = p->sched;
+  return RTA_OK;
+}
+
+rta_status rta_list_schedules(rta_schedule* out, int32_t cap, int32_t* n) {
+  if (!n || cap < 0 || (cap > 0 && !out)) return fail(RTA_E_INVALID_ARG, "bad schedule list arguments");
+  *n = rta::list_schedules(out, cap);
+  return RTA_OK;
+}
+
+rta_status rta_process_batch(rta_pipeline* pipe, const rta_batch* batch, rta_hillas_rec* tel_out,
+                             rta_event_rec* evt_out, rta_stream stream) {
+  rta_status s = check_batch(pipe, batch, tel_out, evt_out);
+  if (s != RTA_OK) return s;
+  return launch_batch(pipe, batch, tel_out, evt_out, (hipStream_t)stream);
+}
+
+rta_status rta_stereo(rta_pipeline* pipe, const int64_t* evt_tel_off, const int32_t* tel_type, int64_t n_evt,
+                      int64_t n_tel, const rta_hillas_rec* tel, rta_event_rec* evt_out, rta_stream stream) {
+  if (!pipe) return fail(RTA_E_INVALID_ARG, "null pipeline");
+  if (n_evt < 0 || n_tel < 0) return fail(RTA_E_INVALID_ARG, "negative count");
+  if (n_evt == 0) return RTA_OK;
+  if (!evt_tel_off || !evt_out || (n_tel > 0 && (!tel_type || !tel))) return fail(RTA_E_INVALID_ARG, "null pointer");
+  rta::EventArgs ea;
+  std::memset(&ea, 0, sizeof(ea));
+  for (size_t i = 0; i < pipe->cams.size(); ++i) ea.focal[i] = pipe->cams[i]->dev.focal;
+  ea.n_types = (int32_t)pipe->cams.size();
+  ea.max_width_ratio = pipe->params.max_width_ratio > 0.f ? pipe->params.max_width_ratio : 0.9f;
+  ea.max_cond = pipe->params.max_cond > 1.f ? pipe->params.max_cond : 1e4f;
+  ea.evt_tel_off = evt_tel_off;
+  ea.tel_type = tel_type;
+  ea.n_evt = n_evt;
+  ea.n_tel = n_tel;
+  ea.tel = tel;
+  ea.out = evt_out;
+  ea.status = pipe->d_status;
+  RTA_HIP(rta::launch_event(ea, (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_batch_status(rta_pipeline* p, uint32_t* status) {
+  if (!p || !status) return fail(RTA_E_INVALID_ARG, "null pipeline or status");
+  RTA_HIP(hipDeviceSynchronize());
+  RTA_HIP(hipMemcpy(status, p->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  RTA_HIP(hipMemset(p->d_status, 0, sizeof(uint32_t)));
+  RTA_HIP(hipDeviceSynchronize());
+  return RTA_OK;
+}
+
+rta_status rta_graph_capture(rta_pipeline* pipe, const rta_batch* batch, rta_hillas_rec* tel_out,
+                             rta_event_rec* evt_out, rta_graph** out) {
+  if (!out) return fail(RTA_E_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  rta_status s = check_batch(pipe, batch, tel_out, evt_out);
+  if (s != RTA_OK) return s;
+  rta_graph* g = new (std::nothrow) rta_graph();
+  if (!g) return fail(RTA_E_NOMEM, "host allocation failed");
+  hipError_t e = hipStreamBeginCapture(pipe->capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    delete g;
+    return fail(RTA_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  s = launch_batch(pipe, batch, tel_out, evt_out, pipe->capture_stream);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(pipe->capture_stream, &graph);
+  if (s != RTA_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    delete g;
+    return s != RTA_OK ? s : fail(RTA_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    delete g;
+    return fail(RTA_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  g->graph = graph;
+  *out = g;
+  return RTA_OK;
+}
+
+rta_status rta_graph_launch(rta_graph* g, rta_stream stream) {
+  if (!g || !g->exec) return fail(RTA_E_INVALID_ARG, "null graph");
+  RTA_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_graph_destroy(rta_graph* g) {
+  if (!g) return RTA_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return RTA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Internal declarations shared by the kernels and the C-ABI layer of librta.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rta.h"
+
+namespace rta {
+
+constexpr int kMaxPix = RTA_MAX_PIX;
+constexpr int kMaxWords = kMaxPix / 64;
+constexpr int kNbrCols = 8;  // device neighbour table: int16 [Npad][8], 16 bytes per pixel
+
+// Device-resident tables of one camera type.  Per-pixel arrays are padded
+// to Npad entries per gain row so that a lane's pixel group loads as one vector.
+struct DevCam {
+  int32_t n_pix, n_pix_pad, n_samp, n_gain;
+  int32_t window, hg_switch;
+  int64_t event_elems;
+  float focal;
+  int32_t pad_;
+  const int32_t* P256;     // [G][Npad] Q8 pedestal per sample
+  const int32_t* thr_pic;  // [G][Npad] Q8 picture threshold (on D)
+  const int32_t* thr_bnd;  // [G][Npad] Q8 boundary threshold (on D)
+  const float* a;          // [G][Npad] ADC per p.e.
+  const float* x;          // [Npad] m
+  const float* y;          // [Npad] m
+  const int16_t* nbr;      // [Npad][8] neighbour indices, -1 padded
+  const uint8_t* border;   // [Npad] 1 if fewer than 6 neighbours
+};
+
+// Passed by value: the camera tables of all types sit in the kernel argument
+// segment and are read with scalar loads at a wave-uniform type index.
+struct FusedArgs {
+  DevCam cams[RTA_MAX_TYPES];
+  int32_t n_types;
+  int32_t window;
+  const uint16_t* traces;
+  int64_t traces_len;
+  const int32_t* tel_type;
+  const int64_t* tel_trace_off;
+  int64_t n_tel;
+  rta_hillas_rec* out;
+  unsigned long long* queue;
+  uint32_t* status;
+};
+
+struct EventArgs {
+  float focal[RTA_MAX_TYPES];
+  int32_t n_types;
+  float max_width_ratio;
+  float max_cond;
+  int32_t pad_;
+  const int64_t* evt_tel_off;
+  const int32_t* tel_type;
+  int64_t n_evt;
+  int64_t n_tel;
+  const rta_hillas_rec* tel;
+  rta_event_rec* out;
+  uint32_t* status;
+};
+
+// Kernel launchers (reco.hip).  Each returns the launch status.
+hipError_t launch_calibrate(const DevCam& c, const uint16_t* traces, int64_t n_evt, int32_t* S, int32_t* D,
+                            uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q, float* t, hipStream_t st);
+hipError_t launch_clean(const DevCam& c, const int32_t* D, const uint8_t* gain, int64_t n_evt, uint8_t* mask,
+                        hipStream_t st);
+hipError_t launch_hillas(const DevCam& c, const int32_t* D, const uint8_t* gain, const float* t,
+                         const uint8_t* mask, int64_t n_evt, rta_hillas_rec* out, hipStream_t st);
+hipError_t launch_queue_reset(unsigned long long* queue, hipStream_t st);
+hipError_t launch_fused(const FusedArgs& a, const rta_schedule& s, int n_cu, hipStream_t st);
+hipError_t launch_event(const EventArgs& a, hipStream_t st);
+
+bool window_supported(int w);
+bool schedule_supported(const rta_schedule& s);
+int list_schedules(rta_schedule* out, int cap);
+
+}  // namespace rta

@@ -1,0 +1,91 @@
+"""The C-ABI library loads and exports every function include/rta.h declares;
+host-side argument checks answer without a GPU.  CPU only."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1307_6489_amd as rta
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rta.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rta_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(rta.LIB_PATH):
+        pytest.fail("librta.so not built; run __graft_entry__.build()")
+    return rta.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(rta.SYMBOLS), set(names) ^ set(rta.SYMBOLS)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes / numpy mirrors have the size and field offsets the C compiler
+    gives the header's structs."""
+    import subprocess
+    structs = {"rta_camera_desc": rta.CameraDesc, "rta_camera_info": rta.CameraInfo, "rta_batch": rta.Batch,
+               "rta_pipeline_params": rta.PipelineParams, "rta_schedule": rta.Schedule}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rta.h"', "int main(void) {"]
+    for cname, ct in structs.items():
+        lines.append('printf("%%zu\\n", sizeof(%s));' % cname)
+        for f, _ in ct._fields_:
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (cname, f))
+    lines.append('printf("%zu\\n%zu\\n", sizeof(rta_hillas_rec), sizeof(rta_event_rec));')
+    lines.append('printf("%zu\\n", offsetof(rta_hillas_rec, flags));')
+    lines.append("return 0; }")
+    src = tmp_path / "sz.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    expect = []
+    for ct in structs.values():
+        expect.append(ctypes.sizeof(ct))
+        expect += [getattr(ct, f).offset for f, _ in ct._fields_]
+    expect += [rta.HILLAS_DTYPE.itemsize, rta.EVENT_DTYPE.itemsize, rta.HILLAS_DTYPE.fields["flags"][1]]
+    assert vals == expect
+
+
+def test_status_strings_and_version(L):
+    assert L.rta_version() == 1
+    assert L.rta_status_str(0) == b"ok"
+    assert L.rta_status_str(2) == b"unsupported shape"
+
+
+def test_schedule_list_is_host_only(L):
+    sched = rta.list_schedules()
+    assert (4, 8, 2) in sched and len(sched) == 24
+
+
+def test_camera_validation_without_device(L):
+    """Shape errors are reported before any device call."""
+    import numpy as np
+    x = np.zeros(4, np.float32)
+    nbr = -np.ones((4, 6), np.int32)
+    ped = np.full(4, 300, np.float32)
+    a = np.full(4, 10, np.float32)
+    for kw, status in ((dict(n_pix=0), 2), (dict(n_pix=4000), 2), (dict(n_gain=3), 2), (dict(window=5), 2),
+                       (dict(n_samp=300), 2), (dict(n_samp=3), 2)):
+        args = dict(n_pix=4, n_samp=30, n_gain=1, window=4)
+        args.update(kw)
+        d = rta.CameraDesc(args["n_pix"], args["n_samp"], args["n_gain"], args["window"], 4000, 6,
+                           rta._ptr(x), rta._ptr(x), rta._ptr(nbr), rta._ptr(ped), rta._ptr(a), 28.0, 10.0, 5.0)
+        h = ctypes.c_void_p()
+        assert L.rta_camera_create(ctypes.byref(d), ctypes.byref(h)) == status, kw
+        assert h.value is None
+    assert L.rta_camera_create(None, None) == 1
+    assert b"null" in L.rta_last_error()
