@@ -65,9 +65,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--pool", type=int, default=3000, help="unique camera events resident in HBM")
     ap.add_argument("--events", type=int, default=1_000_000, help="camera events per step")
-    ap.add_argument("--schedule", type=str, default="", help="pix_per_lane,waves_per_wg,wg_per_cu")
+    ap.add_argument("--schedule", type=str, default="",
+                    help="pix_per_lane,waves_per_wg,wg_per_cu,chunk (default: autotune before timing)")
+    ap.add_argument("--tune-events", type=int, default=200_000,
+                    help="camera events of the stream prefix the autotuner times each schedule on")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-graph", action="store_true", help="eager launches instead of graph replay")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after timing, run a plain 1 GiB elementwise copy kernel twice (reads and writes "
+                         "exactly 2^30 bytes each) to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only; run with --gpus 1", file=sys.stderr)
@@ -85,8 +91,6 @@ def main():
 
     cams = [rta.Camera.from_type(c) for c in pool.cams]
     pipe = rta.Pipeline(cams, do_stereo=False)
-    if args.schedule:
-        pipe.set_schedule(*[int(v) for v in args.schedule.split(",")])
     blob_d = torch.from_numpy(pool.blob).to(dev)
     ty_d = torch.from_numpy(ty).to(dev)
     off_d = torch.from_numpy(off).to(dev)
@@ -94,6 +98,18 @@ def main():
     tel, _ = pipe.alloc_outputs(b, dev)
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
+    tune_info = None
+    if args.schedule:
+        pipe.set_schedule(*[int(v) for v in args.schedule.split(",")])
+    else:
+        from paper_1307_6489_amd import autotune
+        nt = min(args.tune_events, args.events)
+        tb = pipe.make_batch(blob_d, ty_d[:nt], off_d[:nt])
+        best, timings = autotune.tune(pipe, tb, tel[:nt], stream=stream, use_cache=False, log=log)
+        ranked = sorted(timings.items(), key=lambda kv: kv[1])
+        tune_info = {"candidates": len(timings), "tune_events": nt, "best": list(best),
+                     "best_ms": ranked[0][1], "median_ms": ranked[len(ranked) // 2][1], "worst_ms": ranked[-1][1],
+                     "top3": [[list(k), round(v, 4)] for k, v in ranked[:3]]}
 
     with torch.cuda.stream(stream):
         graph = None if args.no_graph else pipe.capture(b, tel)
@@ -154,6 +170,7 @@ def main():
             "camera_events_per_step": n,
             "pool_events": pool.n,
             "schedule": list(pipe.schedule()),
+            "autotune": tune_info,
             "graph": graph is not None,
         },
         "roofline": {
@@ -168,6 +185,13 @@ def main():
             "kernel_ms": kern_ms,
         },
     }
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pool, ty, off)
     print(json.dumps(out), flush=True)

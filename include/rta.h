@@ -166,7 +166,7 @@ typedef struct rta_schedule {
   int32_t pix_per_lane;     /* 2, 4 or 8 pixels per lane (4-, 8- or 16-byte slice loads) */
   int32_t waves_per_wg;     /* 4 or 8 (256 or 512 threads) */
   int32_t wg_per_cu;        /* persistent workgroups per compute unit, 1..4 */
-  int32_t pad_;
+  int32_t chunk;            /* samples per double-buffered load chunk: 8 or 16 */
 } rta_schedule;
 
 const char* rta_status_str(rta_status s);

@@ -67,10 +67,10 @@ class PipelineParams(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("pix_per_lane", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.pix_per_lane, self.waves_per_wg, self.wg_per_cu)
+        return (self.pix_per_lane, self.waves_per_wg, self.wg_per_cu, self.chunk)
 
 
 HILLAS_FIELDS = ("size", "cog_x", "cog_y", "length", "width", "psi", "skewness", "kurtosis",
@@ -278,8 +278,8 @@ class Pipeline:
             _lib.rta_pipeline_destroy(h)
             self.handle = None
 
-    def set_schedule(self, pix_per_lane, waves_per_wg, wg_per_cu):
-        s = Schedule(pix_per_lane, waves_per_wg, wg_per_cu, 0)
+    def set_schedule(self, pix_per_lane, waves_per_wg, wg_per_cu, chunk=8):
+        s = Schedule(pix_per_lane, waves_per_wg, wg_per_cu, chunk)
         _check(lib().rta_set_schedule(self.handle, ctypes.byref(s)))
 
     def schedule(self):

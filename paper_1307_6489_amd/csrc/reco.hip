@@ -46,16 +46,27 @@ __device__ __forceinline__ uint32_t pkmax16(uint32_t a, uint32_t b) {
                             __builtin_elementwise_max(__builtin_bit_cast(us2, a), __builtin_bit_cast(us2, b)));
 }
 
+// Trace loads go through a buffer resource spanning one camera event: the
+// per-lane byte offset (its pixel group) stays in one VGPR and the per-slice
+// offset is wave-uniform, so it rides in the scalar soffset operand.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t event_rsrc(const uint16_t* base, int64_t elems) {
+  // word 3 = 0x00020000: raw 32-bit data format, bounds-checked against num_records
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(base), 0, (int)(elems * 2), 0x00020000);
+}
+
 template <int ND>
-__device__ __forceinline__ void load_slice(uint32_t (&d)[ND], const uint16_t* p) {
+__device__ __forceinline__ void load_slice(uint32_t (&d)[ND], __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   if constexpr (ND == 4) {
-    const uint4 v = *reinterpret_cast<const uint4*>(p);
-    d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    d[0] = v[0]; d[1] = v[1]; d[2] = v[2]; d[3] = v[3];
   } else if constexpr (ND == 2) {
-    const uint2 v = *reinterpret_cast<const uint2*>(p);
-    d[0] = v.x; d[1] = v.y;
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+    d[0] = v[0]; d[1] = v[1];
   } else {
-    d[0] = *reinterpret_cast<const uint32_t*>(p);
+    d[0] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
   }
 }
 
@@ -87,82 +98,92 @@ __device__ __forceinline__ long long uniform_i64(long long v) {
 // the PPL*2 bytes at p0 + k*np.  On return key[p] = max over starts s of
 // (W(s) << 8) | (255 - s): the largest window sum, ties to the smallest s.
 // With TRACK_MAX, rmax holds the packed per-pixel raw maximum over all T.
+//
+// Samples stream in chunks of CH slices, double buffered: the loads of chunk
+// c+1 are in flight while chunk c is reduced, so a wavefront keeps up to 2*CH
+// slice loads outstanding.  Loads past the end of the trace are clamped to the
+// last sample (in bounds, ignored by the uniform k < T guard).
 // ---------------------------------------------------------------------------
-template <int PPL, int W, bool TRACK_MAX>
-__device__ __forceinline__ void window_argmax(const uint16_t* __restrict__ p0, int np, int T, uint32_t (&key)[PPL],
-                                              uint32_t (&rmax)[PPL / 2]) {
-  constexpr int ND = PPL / 2;
-  constexpr int CH = 2 * W;  // samples per unrolled chunk; multiple of W keeps ring indices static
-  uint32_t hist[W][ND];
-  uint32_t ws[PPL];
+template <int PPL, int CH>
+__device__ __forceinline__ void load_chunk(uint32_t (&buf)[CH][PPL / 2], __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                           uint32_t sbase, uint32_t stride, int T, int k0) {
 #pragma unroll
-  for (int k = 0; k < W; ++k) load_slice<ND>(hist[k], p0 + (size_t)k * np);
-#pragma unroll
-  for (int p = 0; p < PPL; ++p) ws[p] = 0;
-#pragma unroll
-  for (int k = 0; k < W; ++k) {
-#pragma unroll
-    for (int h = 0; h < ND; ++h) {
-      ws[2 * h] += lo16(hist[k][h]);
-      ws[2 * h + 1] += hi16(hist[k][h]);
-      if constexpr (TRACK_MAX) rmax[h] = pkmax16(rmax[h], hist[k][h]);
-    }
+  for (int j = 0; j < CH; ++j) {
+    const int k = min(k0 + j, T - 1);
+    load_slice<PPL / 2>(buf[j], r, voff, sbase + (uint32_t)k * stride);
   }
-#pragma unroll
-  for (int p = 0; p < PPL; ++p) key[p] = (ws[p] << 8) | 255u;
+}
 
-  // New sample k enters, sample k - W leaves; both share ring slot k % W.
-  int k0 = W;
-  for (; k0 + CH <= T; k0 += CH) {
-    uint32_t cur[CH][ND];
-#pragma unroll
-    for (int j = 0; j < CH; ++j) load_slice<ND>(cur[j], p0 + (size_t)(k0 + j) * np);
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      const uint32_t sc = 255u - (uint32_t)(k0 + j - W + 1);
-#pragma unroll
-      for (int h = 0; h < ND; ++h) {
-        const uint32_t nw = cur[j][h], od = hist[j % W][h];
-        ws[2 * h] += lo16(nw) - lo16(od);
-        ws[2 * h + 1] += hi16(nw) - hi16(od);
-        key[2 * h] = max(key[2 * h], (ws[2 * h] << 8) | sc);
-        key[2 * h + 1] = max(key[2 * h + 1], (ws[2 * h + 1] << 8) | sc);
-        if constexpr (TRACK_MAX) rmax[h] = pkmax16(rmax[h], nw);
-        hist[j % W][h] = nw;
-      }
-    }
-  }
+// Reduces chunk [k0, k0 + CH).  New sample k and the leaving sample k - W
+// share ring slot k % W = j % W because chunks start at multiples of CH.
+template <int PPL, int W, int CH, bool TRACK_MAX, bool FIRST>
+__device__ __forceinline__ void reduce_chunk(const uint32_t (&buf)[CH][PPL / 2], int k0, int T, uint32_t (&hist)[W][PPL / 2],
+                                             uint32_t (&ws)[PPL], uint32_t (&key)[PPL], uint32_t (&rmax)[PPL / 2]) {
+  constexpr int ND = PPL / 2;
 #pragma unroll
   for (int j = 0; j < CH; ++j) {
     if (k0 + j < T) {
-      uint32_t cur[ND];
-      load_slice<ND>(cur, p0 + (size_t)(k0 + j) * np);
-      const uint32_t sc = 255u - (uint32_t)(k0 + j - W + 1);
 #pragma unroll
       for (int h = 0; h < ND; ++h) {
-        const uint32_t nw = cur[h], od = hist[j % W][h];
-        ws[2 * h] += lo16(nw) - lo16(od);
-        ws[2 * h + 1] += hi16(nw) - hi16(od);
-        key[2 * h] = max(key[2 * h], (ws[2 * h] << 8) | sc);
-        key[2 * h + 1] = max(key[2 * h + 1], (ws[2 * h + 1] << 8) | sc);
+        const uint32_t nw = buf[j][h];
         if constexpr (TRACK_MAX) rmax[h] = pkmax16(rmax[h], nw);
+        if (FIRST && j < W) {
+          ws[2 * h] += lo16(nw);
+          ws[2 * h + 1] += hi16(nw);
+          if (j == W - 1) {
+            key[2 * h] = (ws[2 * h] << 8) | 255u;
+            key[2 * h + 1] = (ws[2 * h + 1] << 8) | 255u;
+          }
+        } else {
+          const uint32_t od = hist[j % W][h];
+          const uint32_t sc = 255u - (uint32_t)(k0 + j - W + 1);
+          ws[2 * h] += lo16(nw) - lo16(od);
+          ws[2 * h + 1] += hi16(nw) - hi16(od);
+          key[2 * h] = max(key[2 * h], (ws[2 * h] << 8) | sc);
+          key[2 * h + 1] = max(key[2 * h + 1], (ws[2 * h + 1] << 8) | sc);
+        }
         hist[j % W][h] = nw;
       }
     }
   }
 }
 
+// r / voff / sbase: buffer resource of the event, this lane's byte offset and
+// the byte offset of the gain block; stride = bytes per slice (2 * Npad).
+template <int PPL, int W, int CH, bool TRACK_MAX>
+__device__ __forceinline__ void window_argmax(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t sbase, uint32_t stride,
+                                              int T, uint32_t (&key)[PPL], uint32_t (&rmax)[PPL / 2]) {
+  static_assert(CH % W == 0 && CH >= W, "chunk must be a multiple of the window");
+  constexpr int ND = PPL / 2;
+  uint32_t hist[W][ND], ws[PPL];
+  uint32_t A[CH][ND], B[CH][ND];
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) ws[p] = 0;
+  const int nchunk = (T + CH - 1) / CH;
+  load_chunk<PPL, CH>(A, r, voff, sbase, stride, T, 0);
+  if (nchunk > 1) load_chunk<PPL, CH>(B, r, voff, sbase, stride, T, CH);
+  reduce_chunk<PPL, W, CH, TRACK_MAX, true>(A, 0, T, hist, ws, key, rmax);
+  for (int c = 1; c < nchunk; c += 2) {
+    if (c + 1 < nchunk) load_chunk<PPL, CH>(A, r, voff, sbase, stride, T, (c + 1) * CH);
+    reduce_chunk<PPL, W, CH, TRACK_MAX, false>(B, c * CH, T, hist, ws, key, rmax);
+    if (c + 1 >= nchunk) break;
+    if (c + 2 < nchunk) load_chunk<PPL, CH>(B, r, voff, sbase, stride, T, (c + 2) * CH);
+    reduce_chunk<PPL, W, CH, TRACK_MAX, false>(A, (c + 1) * CH, T, hist, ws, key, rmax);
+  }
+}
+
 // Extraction of one pixel group on its selected gain.  Returns the bit mask
 // of pixels that switched to low gain.
-template <int PPL, int W>
-__device__ __forceinline__ uint32_t extract_group(const DevCam& c, const uint16_t* __restrict__ ev, int pix0, int np,
-                                                  int T, bool dual, uint32_t (&key)[PPL]) {
+template <int PPL, int W, int CH>
+__device__ __forceinline__ uint32_t extract_group(const DevCam& c, __amdgpu_buffer_rsrc_t r, int pix0, int np, int T,
+                                                  bool dual, uint32_t (&key)[PPL]) {
   uint32_t rmax[PPL / 2];
 #pragma unroll
   for (int h = 0; h < PPL / 2; ++h) rmax[h] = 0;
+  const uint32_t voff = (uint32_t)pix0 * 2u, stride = (uint32_t)np * 2u;
   uint32_t sw = 0;
   if (dual) {
-    window_argmax<PPL, W, true>(ev + pix0, np, T, key, rmax);
+    window_argmax<PPL, W, CH, true>(r, voff, 0u, stride, T, key, rmax);
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
       const uint32_t m = (p & 1) ? hi16(rmax[p >> 1]) : lo16(rmax[p >> 1]);
@@ -170,13 +191,13 @@ __device__ __forceinline__ uint32_t extract_group(const DevCam& c, const uint16_
     }
     if (sw) {
       uint32_t kl[PPL], unused[PPL / 2];
-      window_argmax<PPL, W, false>(ev + (size_t)T * np + pix0, np, T, kl, unused);
+      window_argmax<PPL, W, CH, false>(r, voff, (uint32_t)T * stride, stride, T, kl, unused);
 #pragma unroll
       for (int p = 0; p < PPL; ++p)
         if ((sw >> p) & 1u) key[p] = kl[p];
     }
   } else {
-    window_argmax<PPL, W, false>(ev + pix0, np, T, key, rmax);
+    window_argmax<PPL, W, CH, false>(r, voff, 0u, stride, T, key, rmax);
   }
   return sw;
 }
@@ -264,14 +285,15 @@ __device__ __forceinline__ int mask_slot(const TelSmem& sm, int i) {
 
 // Phase 1 (fused): extraction of all pixels into LDS.  Returns this thread's
 // count of low-gain pixels.
-template <int PPL, int W, int NT>
+template <int PPL, int W, int CH, int NT>
 __device__ __forceinline__ int extract_phase(const DevCam& c, const uint16_t* __restrict__ ev, TelSmem& sm) {
   const int N = c.n_pix, np = c.n_pix_pad, T = c.n_samp;
   const bool dual = c.n_gain == 2;
+  const __amdgpu_buffer_rsrc_t r = event_rsrc(ev, c.event_elems);
   int nlow = 0;
   for (int pix0 = threadIdx.x * PPL; pix0 < N; pix0 += NT * PPL) {
     uint32_t key[PPL];
-    const uint32_t sw = extract_group<PPL, W>(c, ev, pix0, np, T, dual, key);
+    const uint32_t sw = extract_group<PPL, W, CH>(c, r, pix0, np, T, dual, key);
     int32_t P[PPL], Tb[PPL], Tp[PPL];
     load_i32<PPL>(P, c.P256 + pix0);
     load_i32<PPL>(Tb, c.thr_bnd + pix0);
@@ -515,10 +537,10 @@ __device__ __forceinline__ void hillas_phase(const DevCam& c, TelSmem& sm, int n
   if (threadIdx.x == 0) *out = r;
 }
 
-template <int PPL, int W, int NT>
+template <int PPL, int W, int CH, int NT>
 __device__ __forceinline__ void process_telescope(const DevCam& c, const uint16_t* __restrict__ ev, TelSmem& sm,
                                                   rta_hillas_rec* out) {
-  const int nlow = extract_phase<PPL, W, NT>(c, ev, sm);
+  const int nlow = extract_phase<PPL, W, CH, NT>(c, ev, sm);
   __syncthreads();
   mask_phase<NT>(c, sm);
   __syncthreads();
@@ -553,9 +575,10 @@ __global__ __launch_bounds__(NT) void k_calibrate(DevCam c, const uint16_t* __re
   const int N = c.n_pix, np = c.n_pix_pad, T = c.n_samp;
   const uint16_t* ev = traces + e * c.event_elems;
   const size_t ob = (size_t)e * N;
+  const __amdgpu_buffer_rsrc_t r = event_rsrc(ev, c.event_elems);
   for (int pix0 = threadIdx.x * PPL; pix0 < N; pix0 += NT * PPL) {
     uint32_t key[PPL];
-    const uint32_t sw = extract_group<PPL, W>(c, ev, pix0, np, T, c.n_gain == 2, key);
+    const uint32_t sw = extract_group<PPL, W, 2 * W>(c, r, pix0, np, T, c.n_gain == 2, key);
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
       const int i = pix0 + p;
@@ -629,7 +652,7 @@ __global__ void k_queue_reset(unsigned long long* q) {
 // Fused persistent kernel: workgroups pull telescopes from a global counter
 // until the batch is drained; every telescope runs calibration -> cleaning ->
 // Hillas with all intermediates in LDS.
-template <int PPL, int W, int NT>
+template <int PPL, int W, int CH, int NT>
 __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
   __shared__ TelSmem sm;
   __shared__ long long s_tel;
@@ -656,7 +679,7 @@ __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
       }
       continue;
     }
-    process_telescope<PPL, W, NT>(c, a.traces + off, sm, a.out + tel);
+    process_telescope<PPL, W, CH, NT>(c, a.traces + off, sm, a.out + tel);
     __syncthreads();
   }
 }
@@ -751,22 +774,28 @@ hipError_t launch_hillas_w(const DevCam& c, const int32_t* D, const uint8_t* g, 
   return hipGetLastError();
 }
 
-template <int PPL, int W, int NT>
+template <int PPL, int W, int CH, int NT>
 hipError_t launch_fused_t(const FusedArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_fused<PPL, W, NT>), dim3(grid), dim3(NT), 0, st, a);
+  hipLaunchKernelGGL((k_fused<PPL, W, CH, NT>), dim3(grid), dim3(NT), 0, st, a);
   return hipGetLastError();
 }
 
 template <int W>
 hipError_t launch_fused_w(const FusedArgs& a, const rta_schedule& s, int grid, hipStream_t st) {
-  const int key = s.pix_per_lane * 100 + s.waves_per_wg;
+  const int key = s.pix_per_lane * 1000 + s.waves_per_wg * 100 + s.chunk;
   switch (key) {
-    case 204: return launch_fused_t<2, W, 256>(a, grid, st);
-    case 208: return launch_fused_t<2, W, 512>(a, grid, st);
-    case 404: return launch_fused_t<4, W, 256>(a, grid, st);
-    case 408: return launch_fused_t<4, W, 512>(a, grid, st);
-    case 804: return launch_fused_t<8, W, 256>(a, grid, st);
-    case 808: return launch_fused_t<8, W, 512>(a, grid, st);
+    case 2408: return launch_fused_t<2, W, 8, 256>(a, grid, st);
+    case 2416: return launch_fused_t<2, W, 16, 256>(a, grid, st);
+    case 2808: return launch_fused_t<2, W, 8, 512>(a, grid, st);
+    case 2816: return launch_fused_t<2, W, 16, 512>(a, grid, st);
+    case 4408: return launch_fused_t<4, W, 8, 256>(a, grid, st);
+    case 4416: return launch_fused_t<4, W, 16, 256>(a, grid, st);
+    case 4808: return launch_fused_t<4, W, 8, 512>(a, grid, st);
+    case 4816: return launch_fused_t<4, W, 16, 512>(a, grid, st);
+    case 8408: return launch_fused_t<8, W, 8, 256>(a, grid, st);
+    case 8416: return launch_fused_t<8, W, 16, 256>(a, grid, st);
+    case 8808: return launch_fused_t<8, W, 8, 512>(a, grid, st);
+    case 8816: return launch_fused_t<8, W, 16, 512>(a, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -778,18 +807,20 @@ bool window_supported(int w) { return w == 4; }
 bool schedule_supported(const rta_schedule& s) {
   const bool ppl = s.pix_per_lane == 2 || s.pix_per_lane == 4 || s.pix_per_lane == 8;
   const bool wv = s.waves_per_wg == 4 || s.waves_per_wg == 8;
-  return ppl && wv && s.wg_per_cu >= 1 && s.wg_per_cu <= 4;
+  const bool ch = s.chunk == 8 || s.chunk == 16;
+  return ppl && wv && ch && s.wg_per_cu >= 1 && s.wg_per_cu <= 4;
 }
 
 int list_schedules(rta_schedule* out, int cap) {
   int n = 0;
-  const int ppls[3] = {2, 4, 8}, waves[2] = {4, 8};
+  const int ppls[3] = {2, 4, 8}, waves[2] = {4, 8}, chunks[2] = {8, 16};
   for (int p : ppls)
     for (int w : waves)
-      for (int g = 1; g <= 4; ++g) {
-        if (out && n < cap) out[n] = rta_schedule{p, w, g, 0};
-        ++n;
-      }
+      for (int ch : chunks)
+        for (int g = 1; g <= 4; ++g) {
+          if (out && n < cap) out[n] = rta_schedule{p, w, g, ch};
+          ++n;
+        }
   return n;
 }
 

@@ -292,7 +292,7 @@ rta_status rta_pipeline_create(rta_camera* const* cams, int32_t n_types, const r
   p->cams.assign(cams, cams + n_types);
   p->params = *params;
   p->window = cams[0]->dev.window;
-  p->sched = rta_schedule{4, 8, 2, 0};
+  p->sched = rta_schedule{8, 4, 3, 8};
   if (hipGetDevice(&p->device) != hipSuccess ||
       hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) {
     delete p;
@@ -328,7 +328,6 @@ rta_status rta_set_schedule(rta_pipeline* p, const rta_schedule* s) {
   if (!p || !s) return fail(RTA_E_INVALID_ARG, "null pipeline or schedule");
   if (!rta::schedule_supported(*s)) return fail(RTA_E_UNSUPPORTED, "schedule not compiled");
   p->sched = *s;
-  p->sched.pad_ = 0;
   return RTA_OK;
 }
 
