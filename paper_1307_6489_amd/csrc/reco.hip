@@ -91,6 +91,35 @@ __device__ __forceinline__ long long uniform_i64(long long v) {
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((unsigned long long)v >> 32));
   return (long long)(((unsigned long long)hi << 32) | lo);
 }
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  return reinterpret_cast<T*>(uniform_i64(reinterpret_cast<long long>(p)));
+}
+
+// A wave-uniform copy of a camera's tables: every field forced into scalar
+// registers, so loops over samples / pixels and buffer descriptors built from
+// them stay scalar (no per-lane waterfall around buffer loads).
+__device__ __forceinline__ DevCam uniform_cam(const DevCam& c) {
+  DevCam u;
+  u.n_pix = uniform_i32(c.n_pix);
+  u.n_pix_pad = uniform_i32(c.n_pix_pad);
+  u.n_samp = uniform_i32(c.n_samp);
+  u.n_gain = uniform_i32(c.n_gain);
+  u.window = uniform_i32(c.window);
+  u.hg_switch = uniform_i32(c.hg_switch);
+  u.event_elems = uniform_i64(c.event_elems);
+  u.focal = __int_as_float(uniform_i32(__float_as_int(c.focal)));
+  u.pad_ = 0;
+  u.P256 = uniform_ptr(c.P256);
+  u.thr_pic = uniform_ptr(c.thr_pic);
+  u.thr_bnd = uniform_ptr(c.thr_bnd);
+  u.a = uniform_ptr(c.a);
+  u.x = uniform_ptr(c.x);
+  u.y = uniform_ptr(c.y);
+  u.nbr = uniform_ptr(c.nbr);
+  u.border = uniform_ptr(c.border);
+  return u;
+}
 
 // ---------------------------------------------------------------------------
 // Sliding-window argmax over one pixel group.
@@ -101,16 +130,18 @@ __device__ __forceinline__ long long uniform_i64(long long v) {
 //
 // Samples stream in chunks of CH slices, double buffered: the loads of chunk
 // c+1 are in flight while chunk c is reduced, so a wavefront keeps up to 2*CH
-// slice loads outstanding.  Loads past the end of the trace are clamped to the
-// last sample (in bounds, ignored by the uniform k < T guard).
+// slice loads outstanding.  Slices past the end of the trace (the tail of the
+// last chunk) read whatever follows in the event, or 0 beyond the buffer's
+// bounds, and are ignored by the uniform k < T guard.
 // ---------------------------------------------------------------------------
 template <int PPL, int CH>
 __device__ __forceinline__ void load_chunk(uint32_t (&buf)[CH][PPL / 2], __amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                           uint32_t sbase, uint32_t stride, int T, int k0) {
+                                           uint32_t sbase, uint32_t stride, int k0) {
+  uint32_t soff = sbase + (uint32_t)k0 * stride;
 #pragma unroll
   for (int j = 0; j < CH; ++j) {
-    const int k = min(k0 + j, T - 1);
-    load_slice<PPL / 2>(buf[j], r, voff, sbase + (uint32_t)k * stride);
+    load_slice<PPL / 2>(buf[j], r, voff, soff);
+    soff += stride;
   }
 }
 
@@ -160,14 +191,14 @@ __device__ __forceinline__ void window_argmax(__amdgpu_buffer_rsrc_t r, uint32_t
 #pragma unroll
   for (int p = 0; p < PPL; ++p) ws[p] = 0;
   const int nchunk = (T + CH - 1) / CH;
-  load_chunk<PPL, CH>(A, r, voff, sbase, stride, T, 0);
-  if (nchunk > 1) load_chunk<PPL, CH>(B, r, voff, sbase, stride, T, CH);
+  load_chunk<PPL, CH>(A, r, voff, sbase, stride, 0);
+  if (nchunk > 1) load_chunk<PPL, CH>(B, r, voff, sbase, stride, CH);
   reduce_chunk<PPL, W, CH, TRACK_MAX, true>(A, 0, T, hist, ws, key, rmax);
   for (int c = 1; c < nchunk; c += 2) {
-    if (c + 1 < nchunk) load_chunk<PPL, CH>(A, r, voff, sbase, stride, T, (c + 1) * CH);
+    if (c + 1 < nchunk) load_chunk<PPL, CH>(A, r, voff, sbase, stride, (c + 1) * CH);
     reduce_chunk<PPL, W, CH, TRACK_MAX, false>(B, c * CH, T, hist, ws, key, rmax);
     if (c + 1 >= nchunk) break;
-    if (c + 2 < nchunk) load_chunk<PPL, CH>(B, r, voff, sbase, stride, T, (c + 2) * CH);
+    if (c + 2 < nchunk) load_chunk<PPL, CH>(B, r, voff, sbase, stride, (c + 2) * CH);
     reduce_chunk<PPL, W, CH, TRACK_MAX, false>(A, (c + 1) * CH, T, hist, ws, key, rmax);
   }
 }
@@ -189,7 +220,9 @@ __device__ __forceinline__ uint32_t extract_group(const DevCam& c, __amdgpu_buff
       const uint32_t m = (p & 1) ? hi16(rmax[p >> 1]) : lo16(rmax[p >> 1]);
       if ((int)m >= c.hg_switch) sw |= 1u << p;
     }
-    if (sw) {
+    // re-stream the low gain when any lane of the wave owns a switched pixel
+    // (a wave-uniform branch keeps the buffer operands scalar)
+    if (__ballot(sw != 0u)) {
       uint32_t kl[PPL], unused[PPL / 2];
       window_argmax<PPL, W, CH, false>(r, voff, (uint32_t)T * stride, stride, T, kl, unused);
 #pragma unroll
@@ -291,9 +324,14 @@ __device__ __forceinline__ int extract_phase(const DevCam& c, const uint16_t* __
   const bool dual = c.n_gain == 2;
   const __amdgpu_buffer_rsrc_t r = event_rsrc(ev, c.event_elems);
   int nlow = 0;
-  for (int pix0 = threadIdx.x * PPL; pix0 < N; pix0 += NT * PPL) {
+  // Uniform pass loop: every lane streams (loads past the event read 0 from
+  // the bounds-checked buffer); only the stores are guarded by i < N.
+  const int npass = (N + NT * PPL - 1) / (NT * PPL);
+  for (int ps = 0; ps < npass; ++ps) {
+    const int pix0 = (ps * NT + (int)threadIdx.x) * PPL;
     uint32_t key[PPL];
     const uint32_t sw = extract_group<PPL, W, CH>(c, r, pix0, np, T, dual, key);
+    if (pix0 >= N) continue;
     int32_t P[PPL], Tb[PPL], Tp[PPL];
     load_i32<PPL>(P, c.P256 + pix0);
     load_i32<PPL>(Tb, c.thr_bnd + pix0);
@@ -576,7 +614,9 @@ __global__ __launch_bounds__(NT) void k_calibrate(DevCam c, const uint16_t* __re
   const uint16_t* ev = traces + e * c.event_elems;
   const size_t ob = (size_t)e * N;
   const __amdgpu_buffer_rsrc_t r = event_rsrc(ev, c.event_elems);
-  for (int pix0 = threadIdx.x * PPL; pix0 < N; pix0 += NT * PPL) {
+  const int npass = (N + NT * PPL - 1) / (NT * PPL);
+  for (int ps = 0; ps < npass; ++ps) {
+    const int pix0 = (ps * NT + (int)threadIdx.x) * PPL;
     uint32_t key[PPL];
     const uint32_t sw = extract_group<PPL, W, 2 * W>(c, r, pix0, np, T, c.n_gain == 2, key);
 #pragma unroll
@@ -649,9 +689,32 @@ __global__ void k_queue_reset(unsigned long long* q) {
   if (threadIdx.x == 0) *q = 0ull;
 }
 
-// Fused persistent kernel: workgroups pull telescopes from a global counter
-// until the batch is drained; every telescope runs calibration -> cleaning ->
-// Hillas with all intermediates in LDS.
+// Per-telescope body of the fused kernel: descriptor checks, then
+// calibration -> cleaning -> Hillas with all intermediates in LDS.
+template <int PPL, int W, int CH, int NT>
+__device__ __forceinline__ void fused_telescope(const FusedArgs& a, long long tel, TelSmem& sm) {
+  const int ty = uniform_i32(a.tel_type[tel]);
+  const long long off = uniform_i64(a.tel_trace_off[tel]);
+  if (ty < 0 || ty >= a.n_types) {
+    if (threadIdx.x == 0) {
+      bad_record(a.out + tel);
+      atomicOr(a.status, RTA_STATUS_BAD_TYPE);
+    }
+    return;
+  }
+  const DevCam& c = a.cams[ty];
+  if (off < 0 || (off & 7) || off + c.event_elems > a.traces_len) {
+    if (threadIdx.x == 0) {
+      bad_record(a.out + tel);
+      atomicOr(a.status, RTA_STATUS_BAD_OFFSET);
+    }
+    return;
+  }
+  process_telescope<PPL, W, CH, NT>(c, uniform_ptr(a.traces + off), sm, a.out + tel);
+}
+
+// Persistent form: a fixed grid of workgroups pulls telescopes from a global
+// counter until the batch is drained.
 template <int PPL, int W, int CH, int NT>
 __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
   __shared__ TelSmem sm;
@@ -662,26 +725,18 @@ __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
     const long long tel = uniform_i64(s_tel);
     __syncthreads();
     if (tel >= a.n_tel) return;
-    const int ty = uniform_i32(a.tel_type[tel]);
-    const long long off = uniform_i64(a.tel_trace_off[tel]);
-    if (ty < 0 || ty >= a.n_types) {
-      if (threadIdx.x == 0) {
-        bad_record(a.out + tel);
-        atomicOr(a.status, RTA_STATUS_BAD_TYPE);
-      }
-      continue;
-    }
-    const DevCam& c = a.cams[ty];
-    if (off < 0 || (off & 7) || off + c.event_elems > a.traces_len) {
-      if (threadIdx.x == 0) {
-        bad_record(a.out + tel);
-        atomicOr(a.status, RTA_STATUS_BAD_OFFSET);
-      }
-      continue;
-    }
-    process_telescope<PPL, W, CH, NT>(c, a.traces + off, sm, a.out + tel);
+    fused_telescope<PPL, W, CH, NT>(a, tel, sm);
     __syncthreads();
   }
+}
+
+// Grid form: one workgroup per telescope, dispatched by the hardware's
+// workgroup scheduler (no loop-carried state, so no register pressure from
+// values hoisted across telescopes).
+template <int PPL, int W, int CH, int NT>
+__global__ __launch_bounds__(NT) void k_fused_grid(FusedArgs a) {
+  __shared__ TelSmem sm;
+  fused_telescope<PPL, W, CH, NT>(a, (long long)blockIdx.x, sm);
 }
 
 // One wavefront per array event: stereo direction from the telescope records.
@@ -774,9 +829,13 @@ hipError_t launch_hillas_w(const DevCam& c, const int32_t* D, const uint8_t* g, 
   return hipGetLastError();
 }
 
+// grid == 0: one workgroup per telescope; otherwise the persistent form.
 template <int PPL, int W, int CH, int NT>
 hipError_t launch_fused_t(const FusedArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_fused<PPL, W, CH, NT>), dim3(grid), dim3(NT), 0, st, a);
+  if (grid == 0)
+    hipLaunchKernelGGL((k_fused_grid<PPL, W, CH, NT>), dim3((unsigned)a.n_tel), dim3(NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_fused<PPL, W, CH, NT>), dim3(grid), dim3(NT), 0, st, a);
   return hipGetLastError();
 }
 
@@ -808,7 +867,7 @@ bool schedule_supported(const rta_schedule& s) {
   const bool ppl = s.pix_per_lane == 2 || s.pix_per_lane == 4 || s.pix_per_lane == 8;
   const bool wv = s.waves_per_wg == 4 || s.waves_per_wg == 8;
   const bool ch = s.chunk == 8 || s.chunk == 16;
-  return ppl && wv && ch && s.wg_per_cu >= 1 && s.wg_per_cu <= 4;
+  return ppl && wv && ch && s.wg_per_cu >= 0 && s.wg_per_cu <= 4;
 }
 
 int list_schedules(rta_schedule* out, int cap) {
@@ -817,7 +876,7 @@ int list_schedules(rta_schedule* out, int cap) {
   for (int p : ppls)
     for (int w : waves)
       for (int ch : chunks)
-        for (int g = 1; g <= 4; ++g) {
+        for (int g = 0; g <= 4; ++g) {
           if (out && n < cap) out[n] = rta_schedule{p, w, g, ch};
           ++n;
         }
@@ -855,6 +914,7 @@ hipError_t launch_fused(const FusedArgs& a, const rta_schedule& s, int n_cu, hip
   long long grid = (long long)n_cu * s.wg_per_cu;
   if (grid > a.n_tel) grid = a.n_tel;
   if (grid < 1) grid = 1;
+  if (s.wg_per_cu == 0) grid = 0;
   switch (a.window) {
     case 4: return launch_fused_w<4>(a, s, (int)grid, st);
     default: return hipErrorInvalidValue;

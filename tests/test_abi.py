@@ -68,7 +68,7 @@ def test_status_strings_and_version(L):
 
 def test_schedule_list_is_host_only(L):
     sched = rta.list_schedules()
-    assert (8, 4, 3, 8) in sched and len(sched) == 48
+    assert (8, 4, 3, 8) in sched and (8, 4, 0, 8) in sched and len(sched) == 60
 
 
 def test_camera_validation_without_device(L):
