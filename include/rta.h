@@ -235,6 +235,46 @@ rta_status rta_graph_capture(rta_pipeline* pipe, const rta_batch* batch, rta_hil
 rta_status rta_graph_launch(rta_graph* g, rta_stream stream);
 rta_status rta_graph_destroy(rta_graph* g);
 
+/* ------------------------------------------------------------------------
+ * Gamma/hadron + energy network (the separation and energy steps of the
+ * reconstruction products, Section 4.1): 10 per-telescope features ->
+ * 64 -> 64 -> 64 (ReLU) -> [gamma logit, log10(E/TeV)], bfloat16 operands
+ * with FP32 accumulation on the matrix cores, FP32 master weights + Adam.
+ * Features, in order: log10(size), length, width, cog_dist, psi, skewness,
+ * kurtosis, time_gradient, leakage, n_islands; standardised inside the
+ * kernels with the mean / std given to rta_mlp_set_params.
+ * Loss: mean over the batch of BCE(logit, label) + label * (log10 E - y)^2.
+ * Parameters are packed as W1 [10][64], b1 [64], W2 [64][64], b2, W3 [64][64],
+ * b3, W4 [64][2], b4 [2] (W[in][out]), 9154 floats.
+ * ---------------------------------------------------------------------- */
+#define RTA_MLP_N_PARAMS 9154
+#define RTA_MLP_N_FEATURES 10
+
+typedef struct rta_mlp_desc {
+  int32_t max_batch;      /* largest training batch (scratch is sized for it) */
+  float lr, beta1, beta2, eps;  /* Adam */
+} rta_mlp_desc;
+
+rta_status rta_mlp_create(const rta_mlp_desc* desc, rta_mlp** out);
+rta_status rta_mlp_destroy(rta_mlp* m);
+/* HOST arrays: params [RTA_MLP_N_PARAMS], feat_mean / feat_std [10] (std > 0).
+ * Uploads the FP32 masters, rebuilds the bf16 copies, resets Adam.
+ * Synchronous. */
+rta_status rta_mlp_set_params(rta_mlp* m, const float* params, const float* feat_mean, const float* feat_std);
+/* Copies the FP32 master parameters to HOST params [RTA_MLP_N_PARAMS]; synchronous. */
+rta_status rta_mlp_get_params(rta_mlp* m, float* params);
+/* Inference: x [B][10] raw features (device) -> out [B][2] (device). */
+rta_status rta_mlp_forward(rta_mlp* m, const float* x, int64_t B, float* out, rta_stream stream);
+/* Loss and gradient of one batch (B <= max_batch): label [B] (1 gamma, 0
+ * hadron), log10e [B] (used for gammas).  grad: device [RTA_MLP_N_PARAMS]
+ * (NULLABLE), loss: device scalar (NULLABLE).  Weights are not changed. */
+rta_status rta_mlp_loss_grad(rta_mlp* m, const float* x, const float* label, const float* log10e, int64_t B,
+                             float* grad, float* loss, rta_stream stream);
+/* One training step: loss_grad then an Adam update of the masters and the
+ * bf16 copies.  loss: device scalar (NULLABLE). */
+rta_status rta_mlp_train_step(rta_mlp* m, const float* x, const float* label, const float* log10e, int64_t B,
+                              float* loss, rta_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -104,7 +104,21 @@ SYMBOLS = {
     "rta_graph_capture": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "rta_graph_launch": ([_vp, _vp], ctypes.c_int),
     "rta_graph_destroy": ([_vp], ctypes.c_int),
+    "rta_mlp_create": ([_vp, _vp], ctypes.c_int),
+    "rta_mlp_destroy": ([_vp], ctypes.c_int),
+    "rta_mlp_set_params": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+    "rta_mlp_get_params": ([_vp, _vp], ctypes.c_int),
+    "rta_mlp_forward": ([_vp, _vp, _i64, _vp, _vp], ctypes.c_int),
+    "rta_mlp_loss_grad": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp], ctypes.c_int),
+    "rta_mlp_train_step": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
 }
+MLP_N_PARAMS = 9154
+MLP_N_FEATURES = 10
+
+
+class MlpDesc(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 _lib = None
 
@@ -349,3 +363,64 @@ class Graph:
         if h is not None and _lib is not None:
             _lib.rta_graph_destroy(h)
             self.handle = None
+
+
+class Mlp:
+    """The gamma/hadron + energy network on the device (bf16 MFMA kernels)."""
+
+    def __init__(self, max_batch=4096, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        d = MlpDesc(max_batch, lr, beta1, beta2, eps)
+        h = ctypes.c_void_p()
+        _check(lib().rta_mlp_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        self.max_batch = max_batch
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.rta_mlp_destroy(h)
+            self.handle = None
+
+    def set_params(self, params, feat_mean, feat_std):
+        p = np.ascontiguousarray(params, np.float32)
+        m = np.ascontiguousarray(feat_mean, np.float32)
+        s = np.ascontiguousarray(feat_std, np.float32)
+        if p.size != MLP_N_PARAMS or m.size != MLP_N_FEATURES or s.size != MLP_N_FEATURES:
+            raise ValueError("parameter / normaliser sizes")
+        _check(lib().rta_mlp_set_params(self.handle, _ptr(p), _ptr(m), _ptr(s)))
+
+    def get_params(self):
+        p = np.empty(MLP_N_PARAMS, np.float32)
+        _check(lib().rta_mlp_get_params(self.handle, _ptr(p)))
+        return p
+
+    def forward(self, x, stream=None):
+        import torch
+        _require(x, torch.float32, name="x")
+        B = x.shape[0]
+        _require(x, torch.float32, (B, MLP_N_FEATURES), "x")
+        out = torch.empty((B, 2), dtype=torch.float32, device=x.device)
+        _check(lib().rta_mlp_forward(self.handle, _ptr(x), B, _ptr(out), _stream(stream)))
+        return out
+
+    def _batch(self, x, label, log10e):
+        import torch
+        B = x.shape[0]
+        _require(x, torch.float32, (B, MLP_N_FEATURES), "x")
+        _require(label, torch.float32, (B,), "label")
+        _require(log10e, torch.float32, (B,), "log10e")
+        return B
+
+    def loss_grad(self, x, label, log10e, stream=None):
+        import torch
+        B = self._batch(x, label, log10e)
+        grad = torch.empty(MLP_N_PARAMS, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(lib().rta_mlp_loss_grad(self.handle, _ptr(x), _ptr(label), _ptr(log10e), B, _ptr(grad), _ptr(loss),
+                                       _stream(stream)))
+        return loss, grad
+
+    def train_step(self, x, label, log10e, loss_out=None, stream=None):
+        B = self._batch(x, label, log10e)
+        _check(lib().rta_mlp_train_step(self.handle, _ptr(x), _ptr(label), _ptr(log10e), B, _ptr(loss_out),
+                                        _stream(stream)))

@@ -1,0 +1,223 @@
+// Gamma/hadron + energy network on BF16 matrix cores (gfx950 MFMA).
+//
+// The network (10 -> 64 -> 64 -> 64 -> 2, ReLU) maps per-telescope image
+// parameters to a gamma logit and log10(E/TeV); it fills the gamma/hadron
+// separation and energy steps that the paper lists among the reconstruction
+// products (Section 4.1).  Operands are bfloat16, accumulation FP32.
+//
+// Register layout.  Every layer is computed transposed, Z^T = W^T . H^T, with
+// v_mfma_f32_16x16x16_bf16 on 16x16 tiles: A = a 16x16 block of W^T (rows =
+// output features), B = a 16-feature x 16-row block of H^T, C/D = 16 output
+// features x 16 rows.  In that orientation the accumulator layout (lane l:
+// row-of-batch l%16, features 4*(l/16)..+3) is exactly the B-operand layout of
+// the next layer, so activations go from one layer to the next in registers.
+// The backward pass uses the same trick with the untransposed weights.  Weight
+// gradients contract over the batch, so per-row activations and gradients are
+// written feature-major ([F][B], bf16) and one wavefront per 16x16 weight tile
+// runs the batch contraction with the same instruction.
+#include <cmath>
+
+#include "mlp_device.h"
+
+namespace rta {
+using namespace mlpdev;
+constexpr int kRowsNT = 256;  // 4 wavefronts, 16 rows each
+
+namespace {
+
+// Forward (+ loss, + backward to every layer's pre-activation gradient when
+// TRAIN) of 16-row tiles, one per wavefront.
+template <bool TRAIN>
+__global__ __launch_bounds__(kRowsNT) void k_mlp_rows(MlpDev w, const float* __restrict__ x,
+                                                      const float* __restrict__ label,
+                                                      const float* __restrict__ log10e, int B, int Bpad,
+                                                      float* __restrict__ out) {
+  const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+  const int r0 = (blockIdx.x * (kRowsNT / 64) + (threadIdx.x >> 6)) * 16;
+  if (r0 >= Bpad) return;
+  const int b = r0 + col;
+  const bool valid = b < B;
+  const bf16x4 xin = mlp_input_tile(w, x, B, r0);
+  bf16x4 h1[4], h2[4], h3[4];
+  const f32x4 o = mlp_forward_tile(w, xin, h1, h2, h3);
+  if (!TRAIN) {
+    if (grp == 0 && valid) {
+      out[(size_t)b * 2] = o[0];
+      out[(size_t)b * 2 + 1] = o[1];
+    }
+    return;
+  }
+  // loss and output gradient (lanes of group 0 own the two outputs of row b)
+  float g0 = 0.f, g1 = 0.f;
+  if (grp == 0) {
+    float lrow = 0.f;
+    if (valid) {
+      const float z = o[0], e = o[1], lab = label[b], y = log10e[b];
+      const float m = lab > 0.5f ? 1.f : 0.f;
+      const float sig = 1.f / (1.f + expf(-z));
+      lrow = fmaxf(z, 0.f) - z * lab + log1pf(expf(-fabsf(z))) + m * (e - y) * (e - y);
+      g0 = (sig - lab) / (float)B;
+      g1 = 2.f * m * (e - y) / (float)B;
+    }
+    w.loss_row[b] = lrow;
+  }
+  const bf16x4 g4 = pack4(g0, g1, 0.f, 0.f);
+  // store H^T and G4^T (feature-major) for the weight-gradient contraction
+  store4T(w.H0, Bpad, 4 * grp, b, xin);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    store4T(w.H1, Bpad, 16 * t + 4 * grp, b, h1[t]);
+    store4T(w.H2, Bpad, 16 * t + 4 * grp, b, h2[t]);
+    store4T(w.H3, Bpad, 16 * t + 4 * grp, b, h3[t]);
+  }
+  store4T(w.G4, Bpad, 4 * grp, b, g4);
+  // dH3^T = W4 . G4^T, masked -> G3; then G2, G1
+  bf16x4 g3[4], g2[4], g1v[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma(load4(w.W4n, kOutPad, 16 * t + col, 4 * grp), g4, acc);
+    g3[t] = mask_bf(acc, h3[t]);
+    store4T(w.G3, Bpad, 16 * t + 4 * grp, b, g3[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = mfma(load4(w.W3n, kHid, 16 * t + col, 16 * u + 4 * grp), g3[u], acc);
+    g2[t] = mask_bf(acc, h2[t]);
+    store4T(w.G2, Bpad, 16 * t + 4 * grp, b, g2[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = mfma(load4(w.W2n, kHid, 16 * t + col, 16 * u + 4 * grp), g2[u], acc);
+    g1v[t] = mask_bf(acc, h1[t]);
+    store4T(w.G1, Bpad, 16 * t + 4 * grp, b, g1v[t]);
+  }
+}
+
+// Weight / bias gradients and the loss: batch contractions, one wavefront per
+// 16x16 weight tile (40), one per bias vector (4), one for the loss sum.
+constexpr int kGradWaves = 45;
+
+__global__ __launch_bounds__(64) void k_mlp_grad(MlpDev w, int B, int Bpad, float* __restrict__ loss_out) {
+  const int wv = blockIdx.x, lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
+  const int nk = Bpad / 16;
+  if (wv < 40) {
+    // tile -> (layer, input chunk, output chunk)
+    const uint16_t *H, *G;
+    int in0, out0, in_dim, out_dim, off;
+    if (wv < 4) { H = w.H0; G = w.G1; in0 = 0; out0 = 16 * wv; in_dim = kIn; out_dim = kHid; off = kOffW1; }
+    else if (wv < 20) { const int t = wv - 4; H = w.H1; G = w.G2; in0 = 16 * (t / 4); out0 = 16 * (t % 4); in_dim = kHid; out_dim = kHid; off = kOffW2; }
+    else if (wv < 36) { const int t = wv - 20; H = w.H2; G = w.G3; in0 = 16 * (t / 4); out0 = 16 * (t % 4); in_dim = kHid; out_dim = kHid; off = kOffW3; }
+    else { H = w.H3; G = w.G4; in0 = 16 * (wv - 36); out0 = 0; in_dim = kHid; out_dim = kOut; off = kOffW4; }
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < nk; ++k)
+      acc = mfma(load4(H, Bpad, in0 + col, 16 * k + 4 * grp), load4(G, Bpad, out0 + col, 16 * k + 4 * grp), acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = in0 + 4 * grp + i, n = out0 + col;
+      if (m < in_dim && n < out_dim) w.grad[off + m * out_dim + n] = acc[i];
+    }
+  } else if (wv < 44) {
+    const int l = wv - 40;  // bias of layer l+1
+    const uint16_t* G = l == 0 ? w.G1 : l == 1 ? w.G2 : l == 2 ? w.G3 : w.G4;
+    const int nchunk = l == 3 ? 1 : 4, dim = l == 3 ? kOut : kHid;
+    const int off = l == 0 ? kOffB1 : l == 1 ? kOffB2 : l == 2 ? kOffB3 : kOffB4;
+    bf16x4 ones;
+    ones[0] = ones[1] = ones[2] = ones[3] = (short)0x3F80;  // bf16(1.0)
+    for (int c = 0; c < nchunk; ++c) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (int k = 0; k < nk; ++k) acc = mfma(ones, load4(G, Bpad, 16 * c + col, 16 * k + 4 * grp), acc);
+      const int n = 16 * c + col;
+      if (grp == 0 && n < dim) w.grad[off + n] = acc[0];
+    }
+  } else {
+    float s = 0.f;
+    for (int r = lane; r < B; r += 64) s += w.loss_row[r];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) {
+      const float L = s / (float)B;
+      if (loss_out) *loss_out = L;
+      w.loss_row[Bpad] = L;
+    }
+  }
+}
+
+// Parameter index -> bf16 copies in both orientations.
+__device__ __forceinline__ void write_bf16_copies(const MlpDev& w, int p, float v) {
+  const uint16_t h = f2bf(v);
+  if (p < kOffB1) {
+    const int i = p / kHid, o = p % kHid;
+    w.W1t[o * kInPad + i] = h;
+  } else if (p < kOffW2) {
+    w.b1[p - kOffB1] = v;
+  } else if (p < kOffB2) {
+    const int q = p - kOffW2, i = q / kHid, o = q % kHid;
+    w.W2t[o * kHid + i] = h;
+    w.W2n[i * kHid + o] = h;
+  } else if (p < kOffW3) {
+    w.b2[p - kOffB2] = v;
+  } else if (p < kOffB3) {
+    const int q = p - kOffW3, i = q / kHid, o = q % kHid;
+    w.W3t[o * kHid + i] = h;
+    w.W3n[i * kHid + o] = h;
+  } else if (p < kOffW4) {
+    w.b3[p - kOffB3] = v;
+  } else if (p < kOffB4) {
+    const int q = p - kOffW4, i = q / kOut, o = q % kOut;
+    w.W4t[o * kHid + i] = h;
+    w.W4n[i * kOutPad + o] = h;
+  } else {
+    w.b4[p - kOffB4] = v;
+  }
+}
+
+// Adam step on the FP32 master weights (update == 0: only refresh the bf16
+// copies from the masters).  c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t).
+__global__ __launch_bounds__(256) void k_mlp_adam(MlpDev w, int update, float lr, float b1, float b2, float eps,
+                                                  float c1, float c2) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= kNParams) return;
+  float v = w.master[p];
+  if (update) {
+    const float g = w.grad[p];
+    const float m = b1 * w.m1[p] + (1.f - b1) * g;
+    const float s = b2 * w.m2[p] + (1.f - b2) * g * g;
+    w.m1[p] = m;
+    w.m2[p] = s;
+    v -= lr * (m * c1) / (sqrtf(s * c2) + eps);
+    w.master[p] = v;
+  }
+  write_bf16_copies(w, p, v);
+}
+
+}  // namespace
+
+hipError_t launch_mlp_rows(const MlpDev& w, const float* x, const float* label, const float* log10e, int B, int Bpad,
+                           float* out, bool train, hipStream_t st) {
+  const int tiles = Bpad / 16;
+  const int grid = (tiles + 3) / 4;
+  if (train)
+    hipLaunchKernelGGL(k_mlp_rows<true>, dim3(grid), dim3(kRowsNT), 0, st, w, x, label, log10e, B, Bpad, out);
+  else
+    hipLaunchKernelGGL(k_mlp_rows<false>, dim3(grid), dim3(kRowsNT), 0, st, w, x, label, log10e, B, Bpad, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(const MlpDev& w, int B, int Bpad, float* loss_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_grad, dim3(kGradWaves), dim3(64), 0, st, w, B, Bpad, loss_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(const MlpDev& w, bool update, float lr, float b1, float b2, float eps, float c1, float c2,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_adam, dim3((kNParams + 255) / 256), dim3(256), 0, st, w, update ? 1 : 0, lr, b1, b2, eps,
+                     c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace rta

@@ -32,6 +32,15 @@ struct rta_graph {
   hipGraphExec_t exec = nullptr;
 };
 
+struct rta_mlp {
+  rta::MlpDev dev{};
+  void* dmem = nullptr;
+  int max_batch = 0, bpad_max = 0;
+  float lr = 1e-3f, beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+  int64_t step = 0;
+  bool has_params = false;
+};
+
 namespace {
 
 thread_local std::string g_err;
@@ -425,6 +434,141 @@ rta_status rta_graph_destroy(rta_graph* g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
+  return RTA_OK;
+}
+
+rta_status rta_mlp_create(const rta_mlp_desc* d, rta_mlp** out) {
+  if (!d || !out) return fail(RTA_E_INVALID_ARG, "null descriptor or output handle");
+  *out = nullptr;
+  if (d->max_batch < 1 || d->max_batch > (1 << 22)) return fail(RTA_E_SHAPE, "max_batch must be in [1, 2^22]");
+  if (!(d->lr > 0.f) || !(d->beta1 >= 0.f && d->beta1 < 1.f) || !(d->beta2 >= 0.f && d->beta2 < 1.f) ||
+      !(d->eps > 0.f))
+    return fail(RTA_E_INVALID_ARG, "bad Adam hyper-parameters");
+  rta_mlp* m = new (std::nothrow) rta_mlp();
+  if (!m) return fail(RTA_E_NOMEM, "host allocation failed");
+  m->max_batch = d->max_batch;
+  m->bpad_max = (d->max_batch + 63) & ~63;
+  m->lr = d->lr; m->beta1 = d->beta1; m->beta2 = d->beta2; m->eps = d->eps;
+  const size_t P = rta::kNParams, Bp = (size_t)m->bpad_max;
+  // sub-array byte sizes, each rounded to 256
+  const size_t sizes[] = {P * 4, P * 4, P * 4, P * 4,                       // master m1 m2 grad
+                          64 * 16 * 2, 64 * 64 * 2, 64 * 64 * 2, 16 * 64 * 2,  // W1t..W4t
+                          64 * 64 * 2, 64 * 64 * 2, 64 * 16 * 2,             // W2n..W4n
+                          64 * 4, 64 * 4, 64 * 4, 16 * 4, 16 * 4, 16 * 4,     // b1..b4 mean std
+                          16 * Bp * 2, 64 * Bp * 2, 64 * Bp * 2, 64 * Bp * 2,  // H0..H3
+                          64 * Bp * 2, 64 * Bp * 2, 64 * Bp * 2, 16 * Bp * 2,  // G1..G4
+                          (Bp + 1) * 4};
+  const int n = sizeof(sizes) / sizeof(sizes[0]);
+  size_t off[32], total = 0;
+  for (int i = 0; i < n; ++i) { off[i] = total; total += round256(sizes[i]); }
+  if (hipMalloc(&m->dmem, total) != hipSuccess) {
+    delete m;
+    return fail(RTA_E_NOMEM, "device allocation for the network failed");
+  }
+  if (hipMemset(m->dmem, 0, total) != hipSuccess) {
+    (void)hipFree(m->dmem);
+    delete m;
+    return fail(RTA_E_HIP, "clearing network memory failed");
+  }
+  uint8_t* b = static_cast<uint8_t*>(m->dmem);
+  rta::MlpDev& w = m->dev;
+  int i = 0;
+  w.master = (float*)(b + off[i++]); w.m1 = (float*)(b + off[i++]); w.m2 = (float*)(b + off[i++]);
+  w.grad = (float*)(b + off[i++]);
+  w.W1t = (uint16_t*)(b + off[i++]); w.W2t = (uint16_t*)(b + off[i++]); w.W3t = (uint16_t*)(b + off[i++]);
+  w.W4t = (uint16_t*)(b + off[i++]);
+  w.W2n = (uint16_t*)(b + off[i++]); w.W3n = (uint16_t*)(b + off[i++]); w.W4n = (uint16_t*)(b + off[i++]);
+  w.b1 = (float*)(b + off[i++]); w.b2 = (float*)(b + off[i++]); w.b3 = (float*)(b + off[i++]);
+  w.b4 = (float*)(b + off[i++]); w.mean = (float*)(b + off[i++]); w.stdv = (float*)(b + off[i++]);
+  w.H0 = (uint16_t*)(b + off[i++]); w.H1 = (uint16_t*)(b + off[i++]); w.H2 = (uint16_t*)(b + off[i++]);
+  w.H3 = (uint16_t*)(b + off[i++]);
+  w.G1 = (uint16_t*)(b + off[i++]); w.G2 = (uint16_t*)(b + off[i++]); w.G3 = (uint16_t*)(b + off[i++]);
+  w.G4 = (uint16_t*)(b + off[i++]);
+  w.loss_row = (float*)(b + off[i++]);
+  *out = m;
+  return RTA_OK;
+}
+
+rta_status rta_mlp_destroy(rta_mlp* m) {
+  if (!m) return RTA_OK;
+  if (m->dmem) (void)hipFree(m->dmem);
+  delete m;
+  return RTA_OK;
+}
+
+rta_status rta_mlp_set_params(rta_mlp* m, const float* params, const float* mean, const float* stdv) {
+  if (!m || !params || !mean || !stdv) return fail(RTA_E_INVALID_ARG, "null argument");
+  for (int k = 0; k < rta::kNParams; ++k)
+    if (!std::isfinite(params[k])) return fail(RTA_E_INVALID_ARG, "non-finite parameter");
+  float mu[16] = {0}, sd[16];
+  for (int k = 0; k < 16; ++k) sd[k] = 1.f;
+  for (int k = 0; k < RTA_MLP_N_FEATURES; ++k) {
+    if (!std::isfinite(mean[k]) || !std::isfinite(stdv[k]) || !(stdv[k] > 0.f))
+      return fail(RTA_E_INVALID_ARG, "feature mean / std must be finite with std > 0");
+    mu[k] = mean[k];
+    sd[k] = stdv[k];
+  }
+  RTA_HIP(hipMemcpy(m->dev.master, params, sizeof(float) * rta::kNParams, hipMemcpyHostToDevice));
+  RTA_HIP(hipMemset(m->dev.m1, 0, sizeof(float) * rta::kNParams));
+  RTA_HIP(hipMemset(m->dev.m2, 0, sizeof(float) * rta::kNParams));
+  RTA_HIP(hipMemcpy(m->dev.mean, mu, sizeof(mu), hipMemcpyHostToDevice));
+  RTA_HIP(hipMemcpy(m->dev.stdv, sd, sizeof(sd), hipMemcpyHostToDevice));
+  RTA_HIP(rta::launch_mlp_adam(m->dev, false, 0.f, 0.f, 0.f, 1.f, 1.f, 1.f, nullptr));
+  RTA_HIP(hipDeviceSynchronize());
+  m->step = 0;
+  m->has_params = true;
+  return RTA_OK;
+}
+
+rta_status rta_mlp_get_params(rta_mlp* m, float* params) {
+  if (!m || !params) return fail(RTA_E_INVALID_ARG, "null argument");
+  RTA_HIP(hipDeviceSynchronize());
+  RTA_HIP(hipMemcpy(params, m->dev.master, sizeof(float) * rta::kNParams, hipMemcpyDeviceToHost));
+  return RTA_OK;
+}
+
+rta_status rta_mlp_forward(rta_mlp* m, const float* x, int64_t B, float* out, rta_stream stream) {
+  if (!m) return fail(RTA_E_INVALID_ARG, "null network");
+  if (!m->has_params) return fail(RTA_E_INVALID_ARG, "network parameters not set");
+  if (B < 0 || B > 0x7fffffffLL - 64) return fail(RTA_E_SHAPE, "bad batch size");
+  if (B == 0) return RTA_OK;
+  if (!x || !out) return fail(RTA_E_INVALID_ARG, "null input or output");
+  const int Bpad = (int)((B + 63) & ~63LL);
+  RTA_HIP(rta::launch_mlp_rows(m->dev, x, nullptr, nullptr, (int)B, Bpad, out, false, (hipStream_t)stream));
+  return RTA_OK;
+}
+
+static rta_status mlp_loss_grad(rta_mlp* m, const float* x, const float* label, const float* log10e, int64_t B,
+                                float* loss, hipStream_t st) {
+  if (!m) return fail(RTA_E_INVALID_ARG, "null network");
+  if (!m->has_params) return fail(RTA_E_INVALID_ARG, "network parameters not set");
+  if (B < 1 || B > m->max_batch) return fail(RTA_E_SHAPE, "batch must be in [1, max_batch]");
+  if (!x || !label || !log10e) return fail(RTA_E_INVALID_ARG, "null input");
+  const int Bpad = (int)((B + 63) & ~63LL);
+  RTA_HIP(rta::launch_mlp_rows(m->dev, x, label, log10e, (int)B, Bpad, nullptr, true, st));
+  RTA_HIP(rta::launch_mlp_grad(m->dev, (int)B, Bpad, loss, st));
+  return RTA_OK;
+}
+
+rta_status rta_mlp_loss_grad(rta_mlp* m, const float* x, const float* label, const float* log10e, int64_t B,
+                             float* grad, float* loss, rta_stream stream) {
+  rta_status s = mlp_loss_grad(m, x, label, log10e, B, loss, (hipStream_t)stream);
+  if (s != RTA_OK) return s;
+  if (grad)
+    RTA_HIP(hipMemcpyAsync(grad, m->dev.grad, sizeof(float) * rta::kNParams, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_mlp_train_step(rta_mlp* m, const float* x, const float* label, const float* log10e, int64_t B,
+                              float* loss, rta_stream stream) {
+  rta_status s = mlp_loss_grad(m, x, label, log10e, B, loss, (hipStream_t)stream);
+  if (s != RTA_OK) return s;
+  m->step += 1;
+  const double c1 = 1.0 / (1.0 - std::pow((double)m->beta1, (double)m->step));
+  const double c2 = 1.0 / (1.0 - std::pow((double)m->beta2, (double)m->step));
+  RTA_HIP(rta::launch_mlp_adam(m->dev, true, m->lr, m->beta1, m->beta2, m->eps, (float)c1, (float)c2,
+                               (hipStream_t)stream));
   return RTA_OK;
 }
 

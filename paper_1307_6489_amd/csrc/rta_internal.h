@@ -62,6 +62,32 @@ struct EventArgs {
   uint32_t* status;
 };
 
+// Network parameters, packed (matches RTA_MLP_N_PARAMS): W1 [10][64], b1,
+// W2 [64][64], b2, W3 [64][64], b3, W4 [64][2], b4, with W[in][out].
+constexpr int kNParams = 9154;
+constexpr int kOffW1 = 0, kOffB1 = 640, kOffW2 = 704, kOffB2 = 4800, kOffW3 = 4864, kOffB3 = 8960;
+constexpr int kOffW4 = 9024, kOffB4 = 9152;
+
+// Device state of the network: FP32 masters and Adam moments, bf16 working
+// copies in both orientations (t: [out][in] for the forward A operand, n:
+// [in][out] for the backward one), FP32 biases, the feature standardisation,
+// and per-batch scratch (feature-major activations / gradients).
+struct MlpDev {
+  float *master, *m1, *m2, *grad;
+  uint16_t *W1t, *W2t, *W3t, *W4t;  // [64][16], [64][64], [64][64], [16][64]
+  uint16_t *W2n, *W3n, *W4n;        // [64][64], [64][64], [64][16]
+  float *b1, *b2, *b3, *b4;         // [64], [64], [64], [16]
+  float *mean, *stdv;               // [16]
+  uint16_t *H0, *H1, *H2, *H3, *G1, *G2, *G3, *G4;  // [16|64][Bpad]
+  float* loss_row;                  // [Bpad + 1]
+};
+
+hipError_t launch_mlp_rows(const MlpDev& w, const float* x, const float* label, const float* log10e, int B, int Bpad,
+                           float* out, bool train, hipStream_t st);
+hipError_t launch_mlp_grad(const MlpDev& w, int B, int Bpad, float* loss_out, hipStream_t st);
+hipError_t launch_mlp_adam(const MlpDev& w, bool update, float lr, float b1, float b2, float eps, float c1, float c2,
+                           hipStream_t st);
+
 // Kernel launchers (reco.hip).  Each returns the launch status.
 hipError_t launch_calibrate(const DevCam& c, const uint16_t* traces, int64_t n_evt, int32_t* S, int32_t* D,
                             uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q, float* t, hipStream_t st);

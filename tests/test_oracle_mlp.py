@@ -1,0 +1,94 @@
+"""Pins of the network oracle: bfloat16 rounding, closed-form forward,
+loss values, finite-difference gradients and the first Adam step.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+
+def test_bf16_rounding_known_values():
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: ties to even -> 1
+    assert mlp.bf16(np.float32(1 + 2 ** -8)) == 1.0
+    # 1 + 3 * 2^-8 ties between 1 + 2^-7 and 1 + 2^-6: even mantissa -> 1 + 2^-6
+    assert mlp.bf16(np.float32(1 + 3 * 2 ** -8)) == 1 + 2 ** -6
+    assert mlp.bf16(np.float32(1 + 2 ** -8 + 2 ** -20)) == 1 + 2 ** -7      # above the tie rounds up
+    assert mlp.bf16(np.float32(-3.0)) == -3.0
+    assert mlp.bf16(np.float32(0.1)) == 0.10009765625                     # 0x3DCD
+
+
+def test_parameter_count():
+    assert mlp.N_PARAMS == 9154
+
+
+def test_forward_closed_form():
+    """Weights that pass feature 0 through three ReLU layers and read it out:
+    out = (relu chain of 2 x0 + 1) in the logit, 0.5 x1 in the energy."""
+    p = {k: np.zeros(s) for k, s in mlp.SHAPES}
+    p["W1"][0, 0] = 2.0
+    p["b1"][0] = 1.0
+    p["W1"][1, 1] = 1.0
+    p["W2"][0, 0] = 1.0
+    p["W2"][1, 1] = 1.0
+    p["W3"][0, 0] = 1.0
+    p["W3"][1, 1] = 1.0
+    p["W4"][0, 0] = 1.0
+    p["W4"][1, 1] = 0.5
+    theta = mlp.pack(p)
+    x = np.zeros((3, 10))
+    x[:, 0] = [0.25, -2.0, 3.0]
+    x[:, 1] = [1.0, 4.0, -1.0]
+    out, _ = mlp.forward(theta, x)
+    assert np.allclose(out[:, 0], [1.5, 0.0, 7.0])
+    assert np.allclose(out[:, 1], [0.5, 2.0, 0.0])
+
+
+def test_loss_values():
+    out = np.array([[0.0, 1.0], [0.0, 1.0]])
+    L, g = mlp.loss_and_grad_out(out, np.array([1.0, 0.0]), np.array([3.0, 3.0]))
+    # BCE at logit 0 is ln 2 for either label; the gamma adds (1 - 3)^2
+    assert L == pytest.approx((2 * math.log(2) + 4.0) / 2)
+    assert g[:, 0] == pytest.approx([-0.25, 0.25])
+    assert g[:, 1] == pytest.approx([2 * (1.0 - 3.0) / 2, 0.0])
+
+
+def test_backward_matches_finite_differences():
+    """FP64 backward (no bf16 rounding) against central differences."""
+    rng = np.random.default_rng(0)
+    theta = mlp.init_params(1) * 0.7
+    x = rng.normal(size=(12, 10))
+    lab = (rng.random(12) < 0.5).astype(float)
+    y = rng.normal(size=12)
+    L0, g = mlp.loss_grad(theta, x, lab, y, emulate_bf16=False)
+    idx = rng.choice(mlp.N_PARAMS, 120, replace=False)
+    idx = np.concatenate([idx, [0, 639, 640, 9151, 9152, 9153]])
+    h = 1e-6
+    num = []
+    for k in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[k] += h
+        tm[k] -= h
+        num.append((mlp.loss_grad(tp, x, lab, y, False)[0] - mlp.loss_grad(tm, x, lab, y, False)[0]) / (2 * h))
+    num = np.array(num)
+    assert np.linalg.norm(num - g[idx]) <= 1e-6 * max(np.linalg.norm(num), 1e-12)
+
+
+def test_bf16_backward_close_to_exact():
+    """The bf16-emulated gradient is the exact one up to bfloat16 rounding."""
+    rng = np.random.default_rng(2)
+    theta = mlp.init_params(3)
+    x = rng.normal(size=(256, 10))
+    lab = (rng.random(256) < 0.3).astype(float)
+    y = rng.normal(size=256)
+    _, g64 = mlp.loss_grad(theta, x, lab, y, emulate_bf16=False)
+    _, g16 = mlp.loss_grad(theta, x, lab, y, emulate_bf16=True)
+    assert np.linalg.norm(g16 - g64) <= 0.05 * np.linalg.norm(g64)
+
+
+def test_adam_first_step_moves_by_lr_times_sign():
+    opt = mlp.Adam(5, lr=1e-3)
+    theta = np.zeros(5)
+    g = np.array([0.3, -2.0, 1e-3, -1e-2, 5.0])
+    new = opt.step(theta, g)
+    assert np.allclose(new, -1e-3 * np.sign(g), rtol=1e-4)
