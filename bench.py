@@ -71,6 +71,11 @@ def main():
                     help="camera events of the stream prefix the autotuner times each schedule on")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-graph", action="store_true", help="eager launches instead of graph replay")
+    ap.add_argument("--stream-pool", type=int, default=11000,
+                    help="unique camera events of the page-locked host pool (~7.8 GB: two 4 GB chunks)")
+    ap.add_argument("--stream-chunks", type=int, default=24,
+                    help="also stream this many pinned-host chunks of 4 GB through the pipeline (0: skip); "
+                         "reported as the PCIe-inclusive rate, never as value")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run a plain 1 GiB elementwise copy kernel twice (reads and writes "
                          "exactly 2^30 bytes each) to calibrate HBM byte counters")
@@ -185,6 +190,19 @@ def main():
             "kernel_ms": kern_ms,
         },
     }
+    if args.stream_chunks > 0:
+        from paper_1307_6489_amd import stream as st
+        t0 = time.time()
+        hpool = W.c1_pool(args.stream_pool, seed=6)
+        pinned = st.PinnedPool(hpool, 4 << 30)
+        del hpool, blob_d, b, tel
+        torch.cuda.empty_cache()
+        r = st.stream(pipe, pinned, args.stream_chunks, dev)
+        r.update(st.copy_bandwidth(1 << 30, dev))
+        r["pinned_pool_GB"] = pinned.host.numel() * 2 / 1e9
+        out["pinned_stream"] = r
+        log("pinned stream: %s (%.1f s)" % (r, time.time() - t0))
+        del pinned
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -275,6 +275,46 @@ rta_status rta_mlp_loss_grad(rta_mlp* m, const float* x, const float* label, con
 rta_status rta_mlp_train_step(rta_mlp* m, const float* x, const float* label, const float* log10e, int64_t B,
                               float* loss, rta_stream stream);
 
+/* ------------------------------------------------------------------------
+ * Classification with fallback.  Plain scaled-width / scaled-length box cuts
+ * serve as the baseline and as the fallback when a telescope's features are
+ * non-finite or outside the range the network was trained on:
+ *   bin b = clamp(floor((log10 size - lgs_lo) / (lgs_hi - lgs_lo) * n_bins))
+ *   SW = (width - w_mean[b]) / w_std[b],  SL = (length - l_mean[b]) / l_std[b]
+ *   gamma iff SW < cut_w and SL < cut_l;  log10 E = e_a + e_b log10 size.
+ * With the network: score = sigmoid(logit), gamma iff score > mlp_cut.
+ * The tables are prepared from training images by the host (see the Python
+ * package); all per-telescope decisions run in the kernels.
+ * ---------------------------------------------------------------------- */
+#define RTA_BOXCUT_MAX_BINS 32
+
+typedef struct rta_boxcut_desc {
+  int32_t n_bins;                 /* 1..RTA_BOXCUT_MAX_BINS */
+  float lgs_lo, lgs_hi;           /* log10(size) range of the bins */
+  float w_mean[RTA_BOXCUT_MAX_BINS], w_std[RTA_BOXCUT_MAX_BINS];
+  float l_mean[RTA_BOXCUT_MAX_BINS], l_std[RTA_BOXCUT_MAX_BINS];
+  float cut_w, cut_l;
+  float e_a, e_b;
+  float feat_lo[RTA_MLP_N_FEATURES], feat_hi[RTA_MLP_N_FEATURES]; /* trained range */
+  float mlp_cut;                  /* score threshold of the network */
+} rta_boxcut_desc;
+
+/* Network inputs of n Hillas records (device): x [n][10] (device). */
+rta_status rta_features(const rta_hillas_rec* rec, int64_t n, float* x, rta_stream stream);
+
+/* Per-telescope classification of n records (device) -> out [n][4] (device):
+ * gamma score, log10 E, gamma decision (0/1), fallback used (0/1).  m NULLABLE
+ * (box cuts only); bc is HOST memory, read during the call. */
+rta_status rta_classify(rta_mlp* m, const rta_boxcut_desc* bc, const rta_hillas_rec* rec, int64_t n, float* out,
+                        rta_stream stream);
+
+/* Attach (m != NULL) or detach the network and box cuts to a pipeline with
+ * do_stereo: the per-event pass then classifies every telescope, sets
+ * RTA_FLAG_MLP_FALLBACK in records that used the box cuts, and writes the
+ * size-weighted mean score and log10 E to the event record.  The network must
+ * outlive the pipeline or be detached first.  bc: HOST memory. */
+rta_status rta_pipeline_attach_mlp(rta_pipeline* pipe, rta_mlp* m, const rta_boxcut_desc* bc);
+
 #ifdef __cplusplus
 }
 #endif

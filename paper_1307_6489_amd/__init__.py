@@ -111,9 +111,21 @@ SYMBOLS = {
     "rta_mlp_forward": ([_vp, _vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_mlp_loss_grad": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp], ctypes.c_int),
     "rta_mlp_train_step": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
+    "rta_features": ([_vp, _i64, _vp, _vp], ctypes.c_int),
+    "rta_classify": ([_vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
+    "rta_pipeline_attach_mlp": ([_vp, _vp, _vp], ctypes.c_int),
 }
+BOXCUT_MAX_BINS = 32
 MLP_N_PARAMS = 9154
 MLP_N_FEATURES = 10
+
+
+class BoxCutDesc(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("lgs_lo", ctypes.c_float), ("lgs_hi", ctypes.c_float),
+                ("w_mean", ctypes.c_float * 32), ("w_std", ctypes.c_float * 32),
+                ("l_mean", ctypes.c_float * 32), ("l_std", ctypes.c_float * 32),
+                ("cut_w", ctypes.c_float), ("cut_l", ctypes.c_float), ("e_a", ctypes.c_float), ("e_b", ctypes.c_float),
+                ("feat_lo", ctypes.c_float * 10), ("feat_hi", ctypes.c_float * 10), ("mlp_cut", ctypes.c_float)]
 
 
 class MlpDesc(ctypes.Structure):
@@ -336,6 +348,15 @@ class Pipeline:
                                 _ptr(tel_rec), _ptr(out), _stream(stream)))
         return out
 
+    def attach_mlp(self, mlp, boxcut):
+        """Classify telescopes in the per-event pass (mlp None: detach)."""
+        if mlp is None:
+            _check(lib().rta_pipeline_attach_mlp(self.handle, None, None))
+            self._mlp = None
+            return
+        _check(lib().rta_pipeline_attach_mlp(self.handle, mlp.handle, ctypes.byref(boxcut)))
+        self._mlp = mlp
+
     def status(self):
         s = ctypes.c_uint32()
         _check(lib().rta_batch_status(self.handle, ctypes.byref(s)))
@@ -424,3 +445,24 @@ class Mlp:
         B = self._batch(x, label, log10e)
         _check(lib().rta_mlp_train_step(self.handle, _ptr(x), _ptr(label), _ptr(log10e), B, _ptr(loss_out),
                                         _stream(stream)))
+
+
+def features(rec, stream=None):
+    """Network inputs [n][10] of device records ([n][16] float32)."""
+    import torch
+    n = rec.shape[0]
+    _require(rec, torch.float32, (n, 16), "rec")
+    x = torch.empty((n, MLP_N_FEATURES), dtype=torch.float32, device=rec.device)
+    _check(lib().rta_features(_ptr(rec), n, _ptr(x), _stream(stream)))
+    return x
+
+
+def classify(mlp, boxcut, rec, stream=None):
+    """Per-record [score, log10 E, gamma (0/1), fallback (0/1)]; mlp may be None."""
+    import torch
+    n = rec.shape[0]
+    _require(rec, torch.float32, (n, 16), "rec")
+    out = torch.empty((n, 4), dtype=torch.float32, device=rec.device)
+    _check(lib().rta_classify(None if mlp is None else mlp.handle, ctypes.byref(boxcut), _ptr(rec), n, _ptr(out),
+                              _stream(stream)))
+    return out

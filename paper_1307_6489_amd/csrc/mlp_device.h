@@ -107,5 +107,75 @@ __device__ __forceinline__ bf16x4 mlp_input_tile(const MlpDev& w, const float* x
   return pack4(v[0], v[1], v[2], v[3]);
 }
 
+// The 10 network inputs of a Hillas record.
+__device__ __forceinline__ float record_feature(const rta_hillas_rec& r, int f) {
+  switch (f) {
+    case 0: return log10f(r.size);
+    case 1: return r.length;
+    case 2: return r.width;
+    case 3: return r.cog_dist;
+    case 4: return r.psi;
+    case 5: return r.skewness;
+    case 6: return r.kurtosis;
+    case 7: return r.time_gradient;
+    case 8: return r.leakage;
+    default: return (float)r.n_islands;
+  }
+}
+
+// Standardised input tile from records rec[r0 .. r0+15] (rows >= n are 0).
+__device__ __forceinline__ bf16x4 mlp_record_tile(const MlpDev& w, const rta_hillas_rec* rec, int64_t n, int64_t r0) {
+  const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+  float v[4] = {0.f, 0.f, 0.f, 0.f};
+  if (r0 + col < n) {
+    const rta_hillas_rec r = rec[r0 + col];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int f = 4 * grp + j;
+      if (f < kIn) {
+        const float z = (record_feature(r, f) - w.mean[f]) / w.stdv[f];
+        v[j] = isfinite(z) ? z : 0.f;  // non-finite rows fall back to the box cuts
+      }
+    }
+  }
+  return pack4(v[0], v[1], v[2], v[3]);
+}
+
+struct ClassOut {
+  float score, log10e;
+  int gamma, fallback;
+};
+
+// Decision for one record given the network outputs (have_mlp) and the
+// box-cut tables.  The network is used when every feature is finite and
+// inside the trained range; otherwise the box cuts decide.
+__device__ __forceinline__ ClassOut classify_record(const rta_hillas_rec& r, const rta_boxcut_desc& bc, bool have_mlp,
+                                                    float logit, float mlp_e) {
+  ClassOut o;
+  bool in_range = have_mlp;
+#pragma unroll
+  for (int f = 0; f < kIn; ++f) {
+    const float v = record_feature(r, f);
+    in_range = in_range && isfinite(v) && v >= bc.feat_lo[f] && v <= bc.feat_hi[f];
+  }
+  const float lgs = log10f(r.size);
+  if (in_range) {
+    o.score = 1.f / (1.f + expf(-logit));
+    o.log10e = mlp_e;
+    o.gamma = o.score > bc.mlp_cut;
+    o.fallback = 0;
+  } else {
+    int b = (int)floorf((lgs - bc.lgs_lo) / (bc.lgs_hi - bc.lgs_lo) * (float)bc.n_bins);
+    b = b < 0 ? 0 : (b >= bc.n_bins ? bc.n_bins - 1 : b);
+    const float sw = (r.width - bc.w_mean[b]) / bc.w_std[b];
+    const float sl = (r.length - bc.l_mean[b]) / bc.l_std[b];
+    o.gamma = (sw < bc.cut_w) && (sl < bc.cut_l);
+    o.score = o.gamma ? 1.f : 0.f;
+    o.log10e = bc.e_a + bc.e_b * lgs;
+    o.fallback = 1;
+  }
+  return o;
+}
+
 }  // namespace mlpdev
 }  // namespace rta

@@ -27,6 +27,7 @@
 #include <cfloat>
 #include <cmath>
 
+#include "mlp_device.h"
 #include "rta_internal.h"
 
 namespace rta {
@@ -739,7 +740,9 @@ __global__ __launch_bounds__(NT) void k_fused_grid(FusedArgs a) {
   fused_telescope<PPL, W, CH, NT>(a, (long long)blockIdx.x, sm);
 }
 
-// One wavefront per array event: stereo direction from the telescope records.
+// One wavefront per array event: stereo direction from the telescope records
+// and, when enabled, per-telescope classification (network on 16-telescope
+// MFMA tiles, box-cut fallback) aggregated into size-weighted event values.
 constexpr int kEvtNT = 256;
 __global__ __launch_bounds__(kEvtNT) void k_event(EventArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -786,6 +789,40 @@ __global__ __launch_bounds__(kEvtNT) void k_event(EventArgs a) {
 #pragma unroll
     for (int off = kWave / 2; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, kWave);
   }
+  // classification: rows = telescopes of this event, 16 per MFMA tile
+  float c[3] = {0.f, 0.f, 0.f};  // sum size*score, sum size*log10E, sum size
+  if (a.have_box) {
+    const int col = lane & 15, grp = lane >> 4;
+    for (int64_t r0 = lo; r0 < hi; r0 += 16) {
+      float logit = 0.f, me = 0.f;
+      if (a.have_mlp) {
+        mlpdev::bf16x4 h1[4], h2[4], h3[4];
+        const mlpdev::bf16x4 xin = mlpdev::mlp_record_tile(a.mlp, a.tel, hi, r0);
+        const mlpdev::f32x4 o = mlpdev::mlp_forward_tile(a.mlp, xin, h1, h2, h3);
+        logit = o[0];
+        me = o[1];
+      }
+      const int64_t k = r0 + col;
+      if (grp == 0 && k < hi) {
+        rta_hillas_rec h = a.tel[k];
+        const int ty = a.tel_type[k];
+        if (ty >= 0 && ty < a.n_types && !(h.flags & (RTA_FLAG_HILLAS_INVALID | RTA_FLAG_BAD_DESCRIPTOR))) {
+          const mlpdev::ClassOut co = mlpdev::classify_record(h, a.bc, a.have_mlp != 0, logit, me);
+          if (co.fallback) a.tel[k].flags = h.flags | RTA_FLAG_MLP_FALLBACK;
+          if (isfinite(co.log10e) && h.size > 0.f) {
+            c[0] += h.size * co.score;
+            c[1] += h.size * co.log10e;
+            c[2] += h.size;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+      for (int off = kWave / 2; off >= 1; off >>= 1) c[k] += __shfl_xor(c[k], off, kWave);
+    }
+  }
   if (lane == 0) {
     const float A00 = v[0], A01 = v[1], A11 = v[2], b0 = v[3], b1 = v[4];
     const float tr = A00 + A11, det = A00 * A11 - A01 * A01;
@@ -796,7 +833,7 @@ __global__ __launch_bounds__(kEvtNT) void k_event(EventArgs a) {
     r.cond = cond;
     r.n_tel = (int32_t)(hi - lo);
     r.n_used = (int32_t)v[5];
-    r.flags = RTA_EVT_NO_MLP;
+    r.flags = a.have_mlp ? 0u : RTA_EVT_NO_MLP;
     if (r.n_used < 2 || !(cond < a.max_cond)) {
       r.dir_x = r.dir_y = kNaN;
       r.flags |= RTA_EVT_STEREO_INVALID;
@@ -804,7 +841,45 @@ __global__ __launch_bounds__(kEvtNT) void k_event(EventArgs a) {
       r.dir_x = (A11 * b0 - A01 * b1) / det;
       r.dir_y = (A00 * b1 - A01 * b0) / det;
     }
+    if (a.have_box && c[2] > 0.f) {
+      r.gammaness = c[0] / c[2];
+      r.log10_energy = c[1] / c[2];
+    }
     a.out[e] = r;
+  }
+}
+
+// Network inputs of records, one thread per record.
+__global__ __launch_bounds__(256) void k_features(const rta_hillas_rec* __restrict__ rec, int64_t n,
+                                                  float* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const rta_hillas_rec r = rec[i];
+#pragma unroll
+  for (int f = 0; f < mlpdev::kIn; ++f) x[i * mlpdev::kIn + f] = mlpdev::record_feature(r, f);
+}
+
+// Per-record classification, one wavefront per 16 records.
+__global__ __launch_bounds__(256) void k_classify(MlpDev w, int have_mlp, rta_boxcut_desc bc,
+                                                  const rta_hillas_rec* __restrict__ rec, int64_t n,
+                                                  float* __restrict__ out) {
+  const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (r0 >= n) return;
+  float logit = 0.f, me = 0.f;
+  if (have_mlp) {
+    mlpdev::bf16x4 h1[4], h2[4], h3[4];
+    const mlpdev::f32x4 o = mlpdev::mlp_forward_tile(w, mlpdev::mlp_record_tile(w, rec, n, r0), h1, h2, h3);
+    logit = o[0];
+    me = o[1];
+  }
+  const int64_t k = r0 + col;
+  if (grp == 0 && k < n) {
+    const mlpdev::ClassOut co = mlpdev::classify_record(rec[k], bc, have_mlp != 0, logit, me);
+    out[k * 4 + 0] = co.score;
+    out[k * 4 + 1] = co.log10e;
+    out[k * 4 + 2] = (float)co.gamma;
+    out[k * 4 + 3] = (float)co.fallback;
   }
 }
 
@@ -919,6 +994,19 @@ hipError_t launch_fused(const FusedArgs& a, const rta_schedule& s, int n_cu, hip
     case 4: return launch_fused_w<4>(a, s, (int)grid, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_features(const rta_hillas_rec* rec, int64_t n, float* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rec, n, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_classify(const MlpDev& w, bool have_mlp, const rta_boxcut_desc& bc, const rta_hillas_rec* rec,
+                           int64_t n, float* out, hipStream_t st) {
+  const int64_t tiles = (n + 15) / 16;
+  hipLaunchKernelGGL(k_classify, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, w, have_mlp ? 1 : 0, bc, rec, n,
+                     out);
+  return hipGetLastError();
 }
 
 hipError_t launch_event(const EventArgs& a, hipStream_t st) {

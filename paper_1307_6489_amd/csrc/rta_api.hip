@@ -17,6 +17,9 @@ struct rta_camera {
 
 struct rta_pipeline {
   std::vector<rta_camera*> cams;
+  rta_mlp* mlp = nullptr;        // attached network (not owned)
+  bool have_box = false;
+  rta_boxcut_desc bc{};
   rta_pipeline_params params{};
   rta_schedule sched{};
   int window = 0;
@@ -60,6 +63,8 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 size_t round256(size_t v) { return (v + 255) & ~size_t(255); }
 
+void fill_event_args(const rta_pipeline* pipe, rta::EventArgs& ea);
+
 rta_status launch_batch(rta_pipeline* pipe, const rta_batch* b, rta_hillas_rec* tel_out, rta_event_rec* evt_out,
                         hipStream_t st) {
   rta::FusedArgs fa;
@@ -81,11 +86,7 @@ rta_status launch_batch(rta_pipeline* pipe, const rta_batch* b, rta_hillas_rec* 
   }
   if (pipe->params.do_stereo && b->n_evt > 0) {
     rta::EventArgs ea;
-    std::memset(&ea, 0, sizeof(ea));
-    for (size_t i = 0; i < pipe->cams.size(); ++i) ea.focal[i] = pipe->cams[i]->dev.focal;
-    ea.n_types = (int32_t)pipe->cams.size();
-    ea.max_width_ratio = pipe->params.max_width_ratio;
-    ea.max_cond = pipe->params.max_cond;
+    fill_event_args(pipe, ea);
     ea.evt_tel_off = b->evt_tel_off;
     ea.tel_type = b->tel_type;
     ea.n_evt = b->n_evt;
@@ -366,16 +367,12 @@ rta_status rta_stereo(rta_pipeline* pipe, const int64_t* evt_tel_off, const int3
   if (n_evt == 0) return RTA_OK;
   if (!evt_tel_off || !evt_out || (n_tel > 0 && (!tel_type || !tel))) return fail(RTA_E_INVALID_ARG, "null pointer");
   rta::EventArgs ea;
-  std::memset(&ea, 0, sizeof(ea));
-  for (size_t i = 0; i < pipe->cams.size(); ++i) ea.focal[i] = pipe->cams[i]->dev.focal;
-  ea.n_types = (int32_t)pipe->cams.size();
-  ea.max_width_ratio = pipe->params.max_width_ratio > 0.f ? pipe->params.max_width_ratio : 0.9f;
-  ea.max_cond = pipe->params.max_cond > 1.f ? pipe->params.max_cond : 1e4f;
+  fill_event_args(pipe, ea);
   ea.evt_tel_off = evt_tel_off;
   ea.tel_type = tel_type;
   ea.n_evt = n_evt;
   ea.n_tel = n_tel;
-  ea.tel = tel;
+  ea.tel = const_cast<rta_hillas_rec*>(tel);
   ea.out = evt_out;
   ea.status = pipe->d_status;
   RTA_HIP(rta::launch_event(ea, (hipStream_t)stream));
@@ -434,6 +431,55 @@ rta_status rta_graph_destroy(rta_graph* g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
+  return RTA_OK;
+}
+
+static bool boxcut_valid(const rta_boxcut_desc* bc) {
+  if (!bc || bc->n_bins < 1 || bc->n_bins > RTA_BOXCUT_MAX_BINS) return false;
+  if (!std::isfinite(bc->lgs_lo) || !std::isfinite(bc->lgs_hi) || !(bc->lgs_hi > bc->lgs_lo)) return false;
+  for (int b = 0; b < bc->n_bins; ++b)
+    if (!std::isfinite(bc->w_mean[b]) || !std::isfinite(bc->l_mean[b]) || !(bc->w_std[b] > 0.f) ||
+        !(bc->l_std[b] > 0.f))
+      return false;
+  for (int f = 0; f < RTA_MLP_N_FEATURES; ++f)
+    if (std::isnan(bc->feat_lo[f]) || std::isnan(bc->feat_hi[f])) return false;
+  return std::isfinite(bc->e_a) && std::isfinite(bc->e_b) && !std::isnan(bc->cut_w) && !std::isnan(bc->cut_l);
+}
+
+rta_status rta_features(const rta_hillas_rec* rec, int64_t n, float* x, rta_stream stream) {
+  if (n < 0) return fail(RTA_E_INVALID_ARG, "negative count");
+  if (n == 0) return RTA_OK;
+  if (!rec || !x) return fail(RTA_E_INVALID_ARG, "null pointer");
+  if ((n + 255) / 256 > 0x7fffffffLL) return fail(RTA_E_SHAPE, "too many records for one launch");
+  RTA_HIP(rta::launch_features(rec, n, x, (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_classify(rta_mlp* m, const rta_boxcut_desc* bc, const rta_hillas_rec* rec, int64_t n, float* out,
+                        rta_stream stream) {
+  if (!boxcut_valid(bc)) return fail(RTA_E_INVALID_ARG, "invalid box-cut tables");
+  if (m && !m->has_params) return fail(RTA_E_INVALID_ARG, "network parameters not set");
+  if (n < 0) return fail(RTA_E_INVALID_ARG, "negative count");
+  if (n == 0) return RTA_OK;
+  if (!rec || !out) return fail(RTA_E_INVALID_ARG, "null pointer");
+  if ((n + 63) / 64 > 0x7fffffffLL) return fail(RTA_E_SHAPE, "too many records for one launch");
+  rta::MlpDev none{};
+  RTA_HIP(rta::launch_classify(m ? m->dev : none, m != nullptr, *bc, rec, n, out, (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_pipeline_attach_mlp(rta_pipeline* pipe, rta_mlp* m, const rta_boxcut_desc* bc) {
+  if (!pipe) return fail(RTA_E_INVALID_ARG, "null pipeline");
+  if (!m) {
+    pipe->mlp = nullptr;
+    pipe->have_box = false;
+    return RTA_OK;
+  }
+  if (!m->has_params) return fail(RTA_E_INVALID_ARG, "network parameters not set");
+  if (!boxcut_valid(bc)) return fail(RTA_E_INVALID_ARG, "invalid box-cut tables");
+  pipe->mlp = m;
+  pipe->bc = *bc;
+  pipe->have_box = true;
   return RTA_OK;
 }
 
@@ -573,3 +619,17 @@ rta_status rta_mlp_train_step(rta_mlp* m, const float* x, const float* label, co
 }
 
 }  // extern "C"
+
+namespace {
+void fill_event_args(const rta_pipeline* pipe, rta::EventArgs& ea) {
+  std::memset(&ea, 0, sizeof(ea));
+  for (size_t i = 0; i < pipe->cams.size(); ++i) ea.focal[i] = pipe->cams[i]->dev.focal;
+  ea.n_types = (int32_t)pipe->cams.size();
+  ea.max_width_ratio = pipe->params.max_width_ratio > 0.f ? pipe->params.max_width_ratio : 0.9f;
+  ea.max_cond = pipe->params.max_cond > 1.f ? pipe->params.max_cond : 1e4f;
+  ea.have_box = pipe->have_box ? 1 : 0;
+  ea.have_mlp = pipe->mlp ? 1 : 0;
+  if (pipe->mlp) ea.mlp = pipe->mlp->dev;
+  if (pipe->have_box) ea.bc = pipe->bc;
+}
+}  // namespace

@@ -31,37 +31,6 @@ struct DevCam {
   const uint8_t* border;   // [Npad] 1 if fewer than 6 neighbours
 };
 
-// Passed by value: the camera tables of all types sit in the kernel argument
-// segment and are read with scalar loads at a wave-uniform type index.
-struct FusedArgs {
-  DevCam cams[RTA_MAX_TYPES];
-  int32_t n_types;
-  int32_t window;
-  const uint16_t* traces;
-  int64_t traces_len;
-  const int32_t* tel_type;
-  const int64_t* tel_trace_off;
-  int64_t n_tel;
-  rta_hillas_rec* out;
-  unsigned long long* queue;
-  uint32_t* status;
-};
-
-struct EventArgs {
-  float focal[RTA_MAX_TYPES];
-  int32_t n_types;
-  float max_width_ratio;
-  float max_cond;
-  int32_t pad_;
-  const int64_t* evt_tel_off;
-  const int32_t* tel_type;
-  int64_t n_evt;
-  int64_t n_tel;
-  const rta_hillas_rec* tel;
-  rta_event_rec* out;
-  uint32_t* status;
-};
-
 // Network parameters, packed (matches RTA_MLP_N_PARAMS): W1 [10][64], b1,
 // W2 [64][64], b2, W3 [64][64], b3, W4 [64][2], b4, with W[in][out].
 constexpr int kNParams = 9154;
@@ -82,6 +51,41 @@ struct MlpDev {
   float* loss_row;                  // [Bpad + 1]
 };
 
+// Passed by value: the camera tables of all types sit in the kernel argument
+// segment and are read with scalar loads at a wave-uniform type index.
+struct FusedArgs {
+  DevCam cams[RTA_MAX_TYPES];
+  int32_t n_types;
+  int32_t window;
+  const uint16_t* traces;
+  int64_t traces_len;
+  const int32_t* tel_type;
+  const int64_t* tel_trace_off;
+  int64_t n_tel;
+  rta_hillas_rec* out;
+  unsigned long long* queue;
+  uint32_t* status;
+};
+
+struct EventArgs {
+  rta_boxcut_desc bc;
+  MlpDev mlp;
+  int32_t have_mlp;   // network attached (else box cuts only, when have_box)
+  int32_t have_box;   // classification enabled
+  float focal[RTA_MAX_TYPES];
+  int32_t n_types;
+  float max_width_ratio;
+  float max_cond;
+  int32_t pad_;
+  const int64_t* evt_tel_off;
+  const int32_t* tel_type;
+  int64_t n_evt;
+  int64_t n_tel;
+  rta_hillas_rec* tel;
+  rta_event_rec* out;
+  uint32_t* status;
+};
+
 hipError_t launch_mlp_rows(const MlpDev& w, const float* x, const float* label, const float* log10e, int B, int Bpad,
                            float* out, bool train, hipStream_t st);
 hipError_t launch_mlp_grad(const MlpDev& w, int B, int Bpad, float* loss_out, hipStream_t st);
@@ -98,6 +102,9 @@ hipError_t launch_hillas(const DevCam& c, const int32_t* D, const uint8_t* gain,
 hipError_t launch_queue_reset(unsigned long long* queue, hipStream_t st);
 hipError_t launch_fused(const FusedArgs& a, const rta_schedule& s, int n_cu, hipStream_t st);
 hipError_t launch_event(const EventArgs& a, hipStream_t st);
+hipError_t launch_features(const rta_hillas_rec* rec, int64_t n, float* x, hipStream_t st);
+hipError_t launch_classify(const MlpDev& w, bool have_mlp, const rta_boxcut_desc& bc, const rta_hillas_rec* rec,
+                           int64_t n, float* out, hipStream_t st);
 
 bool window_supported(int w);
 bool schedule_supported(const rta_schedule& s);

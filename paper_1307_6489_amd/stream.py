@@ -1,0 +1,120 @@
+"""Pinned-host ingest: stream DL0 chunks to the GPU and reconstruct them.
+
+The real-time analysis receives the DL0 stream from the Central Event Builder
+and must sustain the array's data rate (the paper quotes 0.5-8 GB/s and
+measures host<->GPU copies of page-locked buffers, Section 5).  Here camera
+events sit in a page-locked host pool; chunks of whole events are copied to
+one of two HBM buffers on a copy stream while the fused kernel reconstructs
+the previous chunk on the compute stream (HIP events order the two).  The
+figures are end-to-end and PCIe-bound; the HBM roofline of the kernel is
+measured separately with a device-resident pool.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+import paper_1307_6489_amd as rta
+
+
+class PinnedPool:
+    """A page-locked copy of a generator pool with events in a seeded random
+    order, cut into chunks of whole events of at most ``chunk_bytes``."""
+
+    def __init__(self, pool, chunk_bytes, seed=5):
+        import torch
+        rng = np.random.default_rng(seed)
+        order = rng.permutation(pool.n)
+        elems = np.array([pool.cams[t].event_elems for t in pool.pool_type[order]], np.int64)
+        off = np.zeros(len(order), np.int64)
+        off[1:] = np.cumsum(elems)[:-1]
+        self.host = torch.empty(int(elems.sum()), dtype=torch.uint16, pin_memory=True)
+        h = self.host.numpy()
+        for k, e in enumerate(order):
+            o = int(pool.pool_off[e])
+            h[off[k]:off[k] + elems[k]] = pool.blob[o:o + elems[k]]
+        self.types = pool.pool_type[order].astype(np.int32)
+        self.dl0 = np.array([pool.cams[t].dl0_bytes for t in self.types], np.int64)
+        # chunk boundaries: whole events, at most chunk_bytes each
+        limit = chunk_bytes // 2
+        self.chunks = []
+        start = 0
+        while start < len(order):
+            end = start
+            while end < len(order) and off[end] + elems[end] - off[start] <= limit:
+                end += 1
+            if end == start:
+                raise ValueError("chunk smaller than one event")
+            self.chunks.append((start, end, int(off[start]), int(off[end - 1] + elems[end - 1] - off[start])))
+            start = end
+        self.off = off
+        self.max_chunk_elems = max(c[3] for c in self.chunks)
+
+
+def stream(pipe, pinned: PinnedPool, n_chunks, dev, warmup=2):
+    """Reconstruct ``n_chunks`` chunks (cycling through the pinned pool) with
+    copy / compute overlap.  Returns throughput figures."""
+    import torch
+    copy_s, comp_s = torch.cuda.Stream(), torch.cuda.Stream()
+    bufs = [torch.empty(pinned.max_chunk_elems, dtype=torch.uint16, device=dev) for _ in range(2)]
+    batches, outs = [], []
+    for (s, e, o0, ne) in pinned.chunks:
+        ty = torch.from_numpy(pinned.types[s:e].copy()).to(dev)
+        off = torch.from_numpy((pinned.off[s:e] - o0).astype(np.int64)).to(dev)
+        batches.append((ty, off))
+        outs.append(torch.empty((e - s, 16), dtype=torch.float32, device=dev))
+    copied = [torch.cuda.Event() for _ in range(2)]
+    freed = [torch.cuda.Event() for _ in range(2)]
+    for ev in freed:
+        ev.record(comp_s)
+    torch.cuda.synchronize()
+
+    def run(count, first):
+        n_ev = 0
+        nbytes = 0
+        for i in range(first, first + count):
+            c = i % len(pinned.chunks)
+            s, e, o0, ne = pinned.chunks[c]
+            b = i % 2
+            copy_s.wait_event(freed[b])
+            with torch.cuda.stream(copy_s):
+                bufs[b][:ne].copy_(pinned.host[o0:o0 + ne], non_blocking=True)
+            copied[b].record(copy_s)
+            comp_s.wait_event(copied[b])
+            ty, off = batches[c]
+            bt = pipe.make_batch(bufs[b], ty, off)
+            pipe.process(bt, outs[c], stream=comp_s)
+            freed[b].record(comp_s)
+            n_ev += e - s
+            nbytes += int(pinned.dl0[s:e].sum())
+        return n_ev, nbytes
+
+    run(warmup, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_ev, nbytes = run(n_chunks, warmup)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"camera_events_per_s": n_ev / dt, "dl0_GBps": nbytes / dt / 1e9,
+            "h2d_payload_GBps": sum(pinned.chunks[(warmup + i) % len(pinned.chunks)][3] * 2
+                                    for i in range(n_chunks)) / dt / 1e9,
+            "chunks": n_chunks, "chunk_bytes_max": pinned.max_chunk_elems * 2, "seconds": dt}
+
+
+def copy_bandwidth(nbytes, dev, reps=5):
+    """Page-locked host -> device and device -> host copy rates (GB/s)."""
+    import torch
+    h = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    d = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    res = {}
+    for name, fn in (("h2d_GBps", lambda: d.copy_(h, non_blocking=True)),
+                     ("d2h_GBps", lambda: h.copy_(d, non_blocking=True))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = nbytes * reps / (time.perf_counter() - t0) / 1e9
+    return res

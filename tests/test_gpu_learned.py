@@ -1,0 +1,164 @@
+"""GPU tests of the classification layer and of the learned part.
+
+* features / box cuts / network decisions of rta_classify against the oracle
+  (integer decisions bit-exact, except knife-edge rows whose float32 inputs
+  sit within rounding of a bin edge, a range edge or the score threshold);
+* the per-event pass with an attached network against the oracle's
+  size-weighted aggregation;
+* the benefit test: trained on the GPU kernels, the network beats the plain
+  box cuts in hadron acceptance at equal gamma efficiency (held-out seed).
+"""
+import numpy as np
+import pytest
+
+import dl0sim
+import dl0sim.workloads as W
+import oracle.boxcut as obox
+import paper_1307_6489_amd as rta
+from oracle import mlp as omlp
+from paper_1307_6489_amd import boxcut, learn
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rta.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def small_model(dev):
+    """A network trained on 100k generated images (seed 3, about 780 Adam
+    steps) and a held-out set of 20k (seed 4)."""
+    cam = dl0sim.camera_c0()
+    say("small model: 100k training / 20k held-out images on the 1855-pixel camera")
+    tr = learn.image_features(cam, 100_000, 3, dev)
+    te = learn.image_features(cam, 20_000, 4, dev)
+    net, bc, info = learn.train(tr, dev, epochs=8, batch=1024, lr=2e-3)
+    return cam, tr, te, net, bc, info
+
+
+def rec_tensor(rec, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(rec).view(np.float32).reshape(-1, 16).copy()).to(dev)
+
+
+def test_features_parity(dev, small_model):
+    cam, tr, te, net, bc, info = small_model
+    rec = te["rec"][:5000]
+    x = rta.features(rec_tensor(rec, dev)).cpu().numpy()
+    ref = omlp.features_from_records(rec)
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(x), fin)
+    assert np.allclose(x[fin], ref[fin], rtol=1e-6, atol=0)
+
+
+ULP32 = 2.0 ** -23
+
+
+def knife_edge(bc, feat, score=None):
+    """Rows whose float32 inputs lie within a few float32 ulps of a decision
+    edge (log10 size is computed by each side's own log10 and may differ by
+    one ulp)."""
+    f = np.asarray(feat, np.float64)
+    lo, hi = np.array(bc.feat_lo, np.float64), np.array(bc.feat_hi, np.float64)
+    tol_lo = 4 * ULP32 * np.abs(lo) + 1e-37
+    tol_hi = 4 * ULP32 * np.abs(hi) + 1e-37
+    near_range = np.any(np.isfinite(f) & ((np.abs(f - lo) <= tol_lo) | (np.abs(f - hi) <= tol_hi)), 1)
+    lgs = np.where(np.isfinite(f[:, 0]), f[:, 0], 0.0)
+    near_bin = obox.bin_edge_distance(bc, lgs) < 4 * ULP32 * (np.abs(lgs) + 1.0)
+    edge = near_range | near_bin
+    if score is not None:
+        edge |= np.abs(score - bc.mlp_cut) < 1e-3
+    return edge
+
+
+def test_classify_parity_box_only(dev, small_model):
+    cam, tr, te, net, bc, info = small_model
+    rec = te["rec"]
+    out = rta.classify(None, bc, rec_tensor(rec, dev)).cpu().numpy()
+    feat = omlp.features_from_records(rec).astype(np.float32)
+    s, e, g, fb = obox.classify(bc, feat)
+    ok = ~knife_edge(bc, feat)
+    assert ok.mean() > 0.99
+    assert np.array_equal(out[ok, 2].astype(np.int64), g[ok])
+    assert np.all(out[:, 3] == 1)
+    fin = ok & np.isfinite(e)
+    assert np.allclose(out[fin, 1], e[fin], rtol=1e-5, atol=1e-5)
+
+
+def test_classify_parity_with_network(dev, small_model):
+    import torch
+    cam, tr, te, net, bc, info = small_model
+    rec = te["rec"]
+    out = rta.classify(net, bc, rec_tensor(rec, dev)).cpu().numpy()
+    feat = omlp.features_from_records(rec).astype(np.float32)
+    params = net.get_params().astype(np.float64)
+    ok_x = np.all(np.isfinite(feat), 1)
+    mean = tr["x"][learn.usable(tr["x"], tr["rec"])].mean(0)
+    std = tr["x"][learn.usable(tr["x"], tr["rec"])].std(0) + 1e-6
+    xs = np.zeros_like(feat, dtype=np.float64)
+    xs[ok_x] = ((feat[ok_x] - mean.astype(np.float32)) / std.astype(np.float32)).astype(np.float32)
+    o, _ = omlp.forward(params, xs)
+    s, e, g, fb = obox.classify(bc, feat, o[:, 0], o[:, 1])
+    ok = ~knife_edge(bc, feat, s)
+    assert ok.mean() > 0.98
+    assert np.array_equal(out[ok, 3].astype(np.int64), fb[ok])
+    assert np.array_equal(out[ok, 2].astype(np.int64), g[ok])
+    net_rows = ok & (fb == 0)
+    assert net_rows.sum() > 1000
+    assert np.sqrt(np.mean((out[net_rows, 0] - s[net_rows]) ** 2)) < 1e-3
+
+
+def test_event_pass_with_network(dev, small_model):
+    """Array events through the fused batch with the network attached: event
+    gammaness and log10 E are the size-weighted means of rta_classify."""
+    import torch
+    cam_c0, tr, te, net, bc, info = small_model
+    aw = W.array_events(20, seed=8)
+    cams = [rta.Camera.from_type(c) for c in aw.pool.cams]
+    pipe = rta.Pipeline(cams, do_stereo=True)
+    pipe.attach_mlp(net, bc)
+    b = pipe.make_batch(torch.from_numpy(aw.pool.blob).to(dev), torch.from_numpy(aw.tel_type).to(dev),
+                        torch.from_numpy(aw.tel_off).to(dev), torch.from_numpy(aw.evt_tel_off).to(dev))
+    tel, evt = pipe.alloc_outputs(b, dev)
+    pipe.process(b, tel, evt)
+    cls = rta.classify(net, bc, tel).cpu().numpy()
+    rec = rta.records(tel)
+    ev = rta.records(evt, rta.EVENT_DTYPE)
+    for e in range(len(aw.evt_tel_off) - 1):
+        lo, hi = aw.evt_tel_off[e], aw.evt_tel_off[e + 1]
+        r = rec[lo:hi]
+        c = cls[lo:hi]
+        ok = ((r["flags"] & rta.FLAG_HILLAS_INVALID) == 0) & np.isfinite(c[:, 1]) & (r["size"] > 0)
+        if ok.sum() == 0:
+            assert np.isnan(ev["gammaness"][e])
+            continue
+        w = r["size"][ok].astype(np.float64)
+        assert ev["gammaness"][e] == pytest.approx(np.sum(w * c[ok, 0]) / w.sum(), rel=1e-4, abs=1e-5)
+        assert ev["log10_energy"][e] == pytest.approx(np.sum(w * c[ok, 1]) / w.sum(), rel=1e-4, abs=1e-5)
+        assert (ev["flags"][e] & rta.EVT_NO_MLP) == 0
+        fbk = (r["flags"] & rta.FLAG_MLP_FALLBACK) > 0
+        assert np.array_equal(fbk[ok], c[ok, 3] > 0.5)
+
+
+def test_network_beats_box_cuts(dev, small_model):
+    """At equal gamma efficiency on the held-out seed the network accepts
+    fewer hadrons than the scaled-width/length box cuts (by more than three
+    binomial standard deviations) and estimates log10 E more precisely than
+    the size-only fit."""
+    cam, tr, te, net, bc, info = small_model
+    res = learn.evaluate(net, bc, te, dev, timing_reps=5)
+    say("held-out:", res)
+    assert abs(res["gamma_eff_network"] - res["gamma_eff_box"]) < 0.005
+    diff = res["hadron_acc_box"] - res["hadron_acc_network"]
+    assert diff > 3 * np.hypot(res["hadron_acc_box_err"], res["hadron_acc_network_err"])
+    assert res["log10e_rms_network"] < res["log10e_rms_linear_fit"]
