@@ -58,6 +58,33 @@ def cpu_baseline(pool, ty, off, target_s=10.0):
             "input_GBps": nbytes / t_used / 1e9}
 
 
+def latency_run(args, dev):
+    """Array events with the 2048 x 128 dual-gain type dominating (1:1:8),
+    stereo and the gamma/hadron network attached, fed from page-locked host
+    memory at a paced rate; per-chunk arrival -> event-record latency."""
+    import torch
+    import dl0sim
+    import dl0sim.workloads as W
+    import paper_1307_6489_amd as rta
+    from paper_1307_6489_amd import learn
+    from paper_1307_6489_amd import stream as st
+    t0 = time.time()
+    tr = learn.image_features(dl0sim.camera_c0(), 30_000, 3, dev)
+    net, bc, info = learn.train(tr, dev, epochs=2, batch=1024, lr=2e-3)
+    aw = W.array_events(args.latency_events, seed=5, weights=(1.0, 1.0, 8.0))
+    ps = st.PinnedArrayStream(aw, 8 << 20)
+    cams = [rta.Camera.from_type(c) for c in aw.pool.cams]
+    pipe = rta.Pipeline(cams, do_stereo=True)
+    pipe.set_schedule(*args.latency_schedule)
+    pipe.attach_mlp(net, bc)
+    n_chunks = min(len(ps.chunks), 600)
+    r = st.paced_latency(pipe, ps, args.rate, n_chunks, dev)
+    r["telescopes"] = int(len(aw.tel_type))
+    r["mix"] = "1855x40 : 1764x25 : 2048x128 = 1:1:8, multiplicity 2..40, network + box-cut fallback attached"
+    log("latency run: %s (%.1f s)" % (r, time.time() - t0))
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +103,10 @@ def main():
     ap.add_argument("--stream-chunks", type=int, default=24,
                     help="also stream this many pinned-host chunks of 4 GB through the pipeline (0: skip); "
                          "reported as the PCIe-inclusive rate, never as value")
+    ap.add_argument("--latency-events", type=int, default=400,
+                    help="array events (1:1:8 mix, network attached) paced from pinned host at --rate GB/s "
+                         "for per-event latency (0: skip)")
+    ap.add_argument("--rate", type=float, default=8.0, help="paced DL0 rate for the latency run, GB/s")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run a plain 1 GiB elementwise copy kernel twice (reads and writes "
                          "exactly 2^30 bytes each) to calibrate HBM byte counters")
@@ -203,6 +234,9 @@ def main():
         out["pinned_stream"] = r
         log("pinned stream: %s (%.1f s)" % (r, time.time() - t0))
         del pinned
+    if args.latency_events > 0:
+        args.latency_schedule = pipe.schedule()
+        out["array_latency"] = latency_run(args, dev)
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -118,3 +118,104 @@ def copy_bandwidth(nbytes, dev, reps=5):
         torch.cuda.synchronize()
         res[name] = nbytes * reps / (time.perf_counter() - t0) / 1e9
     return res
+
+
+class PinnedArrayStream:
+    """Page-locked array events cut into chunks of whole array events (at most
+    ``chunk_bytes``), with per-chunk descriptors (offsets relative to the chunk)."""
+
+    def __init__(self, aw, chunk_bytes):
+        import torch
+        pool = aw.pool
+        n_tel = len(aw.tel_type)
+        elems = np.array([pool.cams[t].event_elems for t in aw.tel_type], np.int64)
+        off = np.zeros(n_tel, np.int64)
+        off[1:] = np.cumsum(elems)[:-1]
+        self.host = torch.empty(int(elems.sum()), dtype=torch.uint16, pin_memory=True)
+        h = self.host.numpy()
+        for k in range(n_tel):   # telescopes in event order
+            o = int(aw.tel_off[k])
+            h[off[k]:off[k] + elems[k]] = pool.blob[o:o + elems[k]]
+        self.dl0 = np.array([pool.cams[t].dl0_bytes for t in aw.tel_type], np.int64)
+        E = len(aw.evt_tel_off) - 1
+        limit = chunk_bytes // 2
+        self.chunks = []   # (tel_lo, tel_hi, evt_lo, evt_hi, elem_lo, n_elems)
+        e0 = 0
+        while e0 < E:
+            e1 = e0
+            t_lo = int(aw.evt_tel_off[e0])
+            while e1 < E:
+                t_hi = int(aw.evt_tel_off[e1 + 1])
+                if off[t_hi - 1] + elems[t_hi - 1] - off[t_lo] > limit and e1 > e0:
+                    break
+                e1 += 1
+            t_hi = int(aw.evt_tel_off[e1])
+            self.chunks.append((t_lo, t_hi, e0, e1, int(off[t_lo]), int(off[t_hi - 1] + elems[t_hi - 1] - off[t_lo])))
+            e0 = e1
+        self.tel_type = aw.tel_type
+        self.tel_elem_off = off
+        self.evt_tel_off = aw.evt_tel_off
+        self.max_chunk_elems = max(c[5] for c in self.chunks)
+
+
+def paced_latency(pipe, ps: PinnedArrayStream, rate_GBps, n_chunks, dev, warmup=4):
+    """Submit chunks at the paced DL0 rate (each chunk is released when its
+    last byte would have arrived at ``rate_GBps``), copy, reconstruct with
+    stereo and classification, and time each chunk from its arrival to the
+    completion of its event records (HIP events on the device timeline).
+    Every array event of a chunk completes no later than the chunk, so the
+    chunk latency bounds the latency of each of its events."""
+    import torch
+    copy_s, comp_s = torch.cuda.Stream(), torch.cuda.Stream()
+    nbuf = 3
+    bufs = [torch.empty(ps.max_chunk_elems, dtype=torch.uint16, device=dev) for _ in range(nbuf)]
+    descs = []
+    for (t_lo, t_hi, e_lo, e_hi, o0, ne) in ps.chunks:
+        ty = torch.from_numpy(ps.tel_type[t_lo:t_hi].copy()).to(dev)
+        off = torch.from_numpy((ps.tel_elem_off[t_lo:t_hi] - o0).astype(np.int64)).to(dev)
+        eo = torch.from_numpy((ps.evt_tel_off[e_lo:e_hi + 1] - t_lo).astype(np.int64)).to(dev)
+        tel = torch.empty((t_hi - t_lo, 16), dtype=torch.float32, device=dev)
+        evt = torch.empty((e_hi - e_lo, 8), dtype=torch.float32, device=dev)
+        descs.append((ty, off, eo, tel, evt))
+    freed = [torch.cuda.Event() for _ in range(nbuf)]
+    for ev in freed:
+        ev.record(comp_s)
+    torch.cuda.synchronize()
+    arrive = [torch.cuda.Event(enable_timing=True) for _ in range(n_chunks + warmup)]
+    done = [torch.cuda.Event(enable_timing=True) for _ in range(n_chunks + warmup)]
+    copied = [torch.cuda.Event() for _ in range(n_chunks + warmup)]
+    sizes = [ps.chunks[i % len(ps.chunks)][5] * 2 for i in range(n_chunks + warmup)]
+    t_start = time.perf_counter()
+    due = t_start
+    n_evt = n_tel = nbytes = 0
+    for i in range(n_chunks + warmup):
+        c = i % len(ps.chunks)
+        t_lo, t_hi, e_lo, e_hi, o0, ne = ps.chunks[c]
+        due += sizes[i] / (rate_GBps * 1e9)
+        while time.perf_counter() < due:
+            pass
+        b = i % nbuf
+        arrive[i].record(copy_s)
+        copy_s.wait_event(freed[b])
+        with torch.cuda.stream(copy_s):
+            bufs[b][:ne].copy_(ps.host[o0:o0 + ne], non_blocking=True)
+        copied[i].record(copy_s)
+        comp_s.wait_event(copied[i])
+        ty, off, eo, tel, evt = descs[c]
+        bt = pipe.make_batch(bufs[b], ty, off, eo)
+        pipe.process(bt, tel, evt, stream=comp_s)
+        done[i].record(comp_s)
+        freed[b].record(comp_s)
+        if i >= warmup:
+            n_evt += e_hi - e_lo
+            n_tel += t_hi - t_lo
+            nbytes += int(ps.dl0[t_lo:t_hi].sum())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    lat = np.array([arrive[i].elapsed_time(done[i]) for i in range(warmup, n_chunks + warmup)])
+    span = arrive[warmup].elapsed_time(done[-1]) * 1e-3
+    return {"array_events_per_s": n_evt / span, "camera_events_per_s": n_tel / span,
+            "dl0_GBps": nbytes / span / 1e9, "paced_GBps": rate_GBps,
+            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+            "latency_ms_max": float(lat.max()), "chunks": n_chunks,
+            "chunk_bytes_mean": float(np.mean(sizes[warmup:])), "wall_s": wall}
