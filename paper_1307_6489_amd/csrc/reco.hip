@@ -146,61 +146,104 @@ __device__ __forceinline__ void load_chunk(uint32_t (&buf)[CH][PPL / 2], __amdgp
   }
 }
 
-// Reduces chunk [k0, k0 + CH).  New sample k and the leaving sample k - W
-// share ring slot k % W = j % W because chunks start at multiples of CH.
-template <int PPL, int W, int CH, bool TRACK_MAX, bool FIRST>
-__device__ __forceinline__ void reduce_chunk(const uint32_t (&buf)[CH][PPL / 2], int k0, int T, uint32_t (&hist)[W][PPL / 2],
-                                             uint32_t (&ws)[PPL], uint32_t (&key)[PPL], uint32_t (&rmax)[PPL / 2]) {
+// Slice j of the chunk starting at k0 enters the window whose start is
+// k0 + j - W + 1; the sample leaving it is slice j - W of the same chunk, or
+// slice CH + j - W of the previous chunk (still intact: the next prefetch into
+// that buffer is issued only after the first W slices are reduced).
+//
+// Within a chunk the candidates are ranked by a chunk-local key
+// (W << 4) | (15 - j): the largest sum, then the earliest slice, with an
+// inline-constant low part.  merge_chunk folds the chunk's best into the
+// global key (W << 8) | (255 - s).
+template <int PPL, int W, int CH, bool TRACK_MAX, bool GUARD, bool FIRST, int J0, int J1>
+__device__ __forceinline__ void reduce_slices(const uint32_t (&cur)[CH][PPL / 2], const uint32_t (&prev)[CH][PPL / 2],
+                                              int k0, int T, uint32_t (&ws)[PPL], uint32_t (&loc)[PPL],
+                                              uint32_t (&rmax)[PPL / 2]) {
   constexpr int ND = PPL / 2;
 #pragma unroll
-  for (int j = 0; j < CH; ++j) {
-    if (k0 + j < T) {
+  for (int j = J0; j < J1; ++j) {
+    if (GUARD && k0 + j >= T) continue;
 #pragma unroll
-      for (int h = 0; h < ND; ++h) {
-        const uint32_t nw = buf[j][h];
-        if constexpr (TRACK_MAX) rmax[h] = pkmax16(rmax[h], nw);
-        if (FIRST && j < W) {
-          ws[2 * h] += lo16(nw);
-          ws[2 * h + 1] += hi16(nw);
-          if (j == W - 1) {
-            key[2 * h] = (ws[2 * h] << 8) | 255u;
-            key[2 * h + 1] = (ws[2 * h + 1] << 8) | 255u;
-          }
-        } else {
-          const uint32_t od = hist[j % W][h];
-          const uint32_t sc = 255u - (uint32_t)(k0 + j - W + 1);
-          ws[2 * h] += lo16(nw) - lo16(od);
-          ws[2 * h + 1] += hi16(nw) - hi16(od);
-          key[2 * h] = max(key[2 * h], (ws[2 * h] << 8) | sc);
-          key[2 * h + 1] = max(key[2 * h + 1], (ws[2 * h + 1] << 8) | sc);
+    for (int h = 0; h < ND; ++h) {
+      const uint32_t nw = cur[j][h];
+      if constexpr (TRACK_MAX) rmax[h] = pkmax16(rmax[h], nw);
+      if (FIRST && j < W) {
+        ws[2 * h] += lo16(nw);
+        ws[2 * h + 1] += hi16(nw);
+        if (j == W - 1) {
+          loc[2 * h] = max(loc[2 * h], (ws[2 * h] << 4) | (uint32_t)(15 - j));
+          loc[2 * h + 1] = max(loc[2 * h + 1], (ws[2 * h + 1] << 4) | (uint32_t)(15 - j));
         }
-        hist[j % W][h] = nw;
+      } else {
+        const uint32_t od = (j >= W) ? cur[j - W][h] : prev[CH + j - W][h];
+        ws[2 * h] += lo16(nw) - lo16(od);
+        ws[2 * h + 1] += hi16(nw) - hi16(od);
+        loc[2 * h] = max(loc[2 * h], (ws[2 * h] << 4) | (uint32_t)(15 - j));
+        loc[2 * h + 1] = max(loc[2 * h + 1], (ws[2 * h + 1] << 4) | (uint32_t)(15 - j));
       }
     }
   }
 }
 
-// r / voff / sbase: buffer resource of the event, this lane's byte offset and
-// the byte offset of the gain block; stride = bytes per slice (2 * Npad).
+// Global key from the chunk-local best: start s = k0 + j - W + 1, so
+// 255 - s = (254 - k0 + W - 15) + (15 - j).
+template <int PPL, int W>
+__device__ __forceinline__ void merge_chunk(int k0, uint32_t (&loc)[PPL], uint32_t (&key)[PPL]) {
+  const uint32_t c = (uint32_t)(254 - k0 + W - 15);
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    const uint32_t cand = ((loc[p] >> 4) << 8) | (c + (loc[p] & 15u));
+    key[p] = max(key[p], cand);
+    loc[p] = 0;
+  }
+}
+
+template <int PPL, int W, int CH, bool TRACK_MAX, bool GUARD, bool FIRST>
+__device__ __forceinline__ void reduce_chunk(const uint32_t (&cur)[CH][PPL / 2], const uint32_t (&prev)[CH][PPL / 2],
+                                             int k0, int T, uint32_t (&ws)[PPL], uint32_t (&loc)[PPL],
+                                             uint32_t (&key)[PPL], uint32_t (&rmax)[PPL / 2]) {
+  reduce_slices<PPL, W, CH, TRACK_MAX, GUARD, FIRST, 0, CH>(cur, prev, k0, T, ws, loc, rmax);
+  merge_chunk<PPL, W>(k0, loc, key);
+}
+
 template <int PPL, int W, int CH, bool TRACK_MAX>
 __device__ __forceinline__ void window_argmax(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t sbase, uint32_t stride,
                                               int T, uint32_t (&key)[PPL], uint32_t (&rmax)[PPL / 2]) {
-  static_assert(CH % W == 0 && CH >= W, "chunk must be a multiple of the window");
+  static_assert(CH % W == 0 && CH >= W && CH <= 16, "chunk must be a multiple of the window, at most 16");
   constexpr int ND = PPL / 2;
-  uint32_t hist[W][ND], ws[PPL];
+  uint32_t ws[PPL], loc[PPL];
   uint32_t A[CH][ND], B[CH][ND];
 #pragma unroll
-  for (int p = 0; p < PPL; ++p) ws[p] = 0;
+  for (int p = 0; p < PPL; ++p) { ws[p] = 0; loc[p] = 0; key[p] = 0; }
   const int nchunk = (T + CH - 1) / CH;
+  const int nfull = T / CH;  // chunks with all CH slices inside the trace
   load_chunk<PPL, CH>(A, r, voff, sbase, stride, 0);
   if (nchunk > 1) load_chunk<PPL, CH>(B, r, voff, sbase, stride, CH);
-  reduce_chunk<PPL, W, CH, TRACK_MAX, true>(A, 0, T, hist, ws, key, rmax);
+  if (nfull >= 1)
+    reduce_chunk<PPL, W, CH, TRACK_MAX, false, true>(A, A, 0, T, ws, loc, key, rmax);
+  else
+    reduce_chunk<PPL, W, CH, TRACK_MAX, true, true>(A, A, 0, T, ws, loc, key, rmax);
+  // Chunk c lives in B (odd c) or A (even c); the other buffer holds c - 1.
   for (int c = 1; c < nchunk; c += 2) {
-    if (c + 1 < nchunk) load_chunk<PPL, CH>(A, r, voff, sbase, stride, (c + 1) * CH);
-    reduce_chunk<PPL, W, CH, TRACK_MAX, false>(B, c * CH, T, hist, ws, key, rmax);
+    const int k0 = c * CH;
+    if (c < nfull) {
+      reduce_slices<PPL, W, CH, TRACK_MAX, false, false, 0, W>(B, A, k0, T, ws, loc, rmax);
+      if (c + 1 < nchunk) load_chunk<PPL, CH>(A, r, voff, sbase, stride, k0 + CH);
+      reduce_slices<PPL, W, CH, TRACK_MAX, false, false, W, CH>(B, A, k0, T, ws, loc, rmax);
+    } else {
+      reduce_slices<PPL, W, CH, TRACK_MAX, true, false, 0, CH>(B, A, k0, T, ws, loc, rmax);
+    }
+    merge_chunk<PPL, W>(k0, loc, key);
     if (c + 1 >= nchunk) break;
-    if (c + 2 < nchunk) load_chunk<PPL, CH>(B, r, voff, sbase, stride, (c + 2) * CH);
-    reduce_chunk<PPL, W, CH, TRACK_MAX, false>(A, (c + 1) * CH, T, hist, ws, key, rmax);
+    const int k1 = k0 + CH;
+    if (c + 1 < nfull) {
+      reduce_slices<PPL, W, CH, TRACK_MAX, false, false, 0, W>(A, B, k1, T, ws, loc, rmax);
+      if (c + 2 < nchunk) load_chunk<PPL, CH>(B, r, voff, sbase, stride, k1 + CH);
+      reduce_slices<PPL, W, CH, TRACK_MAX, false, false, W, CH>(A, B, k1, T, ws, loc, rmax);
+    } else {
+      reduce_slices<PPL, W, CH, TRACK_MAX, true, false, 0, CH>(A, B, k1, T, ws, loc, rmax);
+    }
+    merge_chunk<PPL, W>(k1, loc, key);
   }
 }
 
