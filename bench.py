@@ -3,8 +3,8 @@
 Workload (the mixed-camera throughput configuration): dual-gain uint16 traces
 of 1855-px x 40-sample, 1764-px x 25-sample and 2048-px x 128-sample cameras
 in ratio 1:3:6, plain ellipse images.  A seeded pool of unique camera events
-(default 3000, about 2.1 GB, far larger than the 256 MB last-level cache) is
-made resident in HBM; one step is one pass of calibration -> cleaning ->
+(default 24000, about 17 GB: re-reads of a pool a few times the size of the
+256 MB last-level cache still hit it measurably) is made resident in HBM; one step is one pass of calibration -> cleaning ->
 Hillas over 1e6 camera events streamed through the pool in a seeded random
 order, replayed from a captured HIP graph.  Inputs are resident before the
 timed region starts.
@@ -28,6 +28,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+
+# HBM traffic of the fused kernel from two rocprofv3 --pmc passes (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch) on this workload, each scaled by what the
+# counter reads for a plain copy of 2^30 bytes (FETCH_SIZE reads 2^19 KiB:
+# factor 2.0; WRITE_SIZE reads 2^20 KiB: factor 1.0).  Valid only for the
+# kernel sources, schedule and workload it was taken on; reported as null
+# otherwise.
+COUNTER_SOURCES = ("paper_1307_6489_amd/csrc/reco.hip", "paper_1307_6489_amd/csrc/rta_internal.h")
+MEASURED_TRAFFIC = {
+    "sources": "2669cee41d5904c0", "schedule": (8, 4, 0, 8), "pool_events": 24000, "events": 1_000_000,
+    "fetch_kib": 180694329.5, "fetch_factor": 2.0, "write_kib": 62500.02, "write_factor": 1.0,
+}
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in COUNTER_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(schedule, pool_n, events):
+    m = MEASURED_TRAFFIC
+    if m is None or m["sources"] != sources_digest() or list(m["schedule"]) != list(schedule) \
+            or m["pool_events"] != pool_n or m["events"] != events:
+        return None
+    return m["fetch_kib"] * 1024 * m["fetch_factor"] + m["write_kib"] * 1024 * m["write_factor"]
 
 
 def log(*a):
@@ -85,12 +114,67 @@ def latency_run(args, dev):
     return r
 
 
+def array_batch_run(args, dev, stream):
+    """Batched array events: ragged array events of multiplicity 2..40 over
+    the three camera types (1:3:6), replicated from a device-resident pool of
+    rendered array events, through one graph-replayed rta_process_batch with
+    stereo per array event; schedule from the autotuner on a telescope prefix."""
+    import torch
+    import dl0sim.workloads as W
+    import paper_1307_6489_amd as rta
+    from paper_1307_6489_amd import autotune
+    t0 = time.time()
+    aw = W.array_events(args.array_pool, seed=2)
+    eo, ty, off, _ = W.replicate_array_events(aw, args.array_events, seed=9)
+    log("array pool: %d array events, %d telescopes, %.2f GB, generated in %.1f s"
+        % (args.array_pool, len(aw.tel_type), aw.pool.blob.nbytes / 1e9, time.time() - t0))
+    cams = [rta.Camera.from_type(c) for c in aw.pool.cams]
+    pipe = rta.Pipeline(cams, do_stereo=True)
+    blob_d = torch.from_numpy(aw.pool.blob).to(dev)
+    ty_d, off_d, eo_d = (torch.from_numpy(v).to(dev) for v in (ty, off, eo))
+    b = pipe.make_batch(blob_d, ty_d, off_d, eo_d)
+    tel, evt = pipe.alloc_outputs(b, dev)
+    nt = min(args.tune_events, len(ty))
+    tb = pipe.make_batch(blob_d, ty_d[:nt], off_d[:nt])
+    best, timings = autotune.tune(pipe, tb, tel[:nt], stream=stream, use_cache=False)
+    with torch.cuda.stream(stream):
+        graph = pipe.capture(b, tel, evt)
+        graph.launch(stream)
+        stream.synchronize()
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t1 = time.perf_counter()
+        a.record(stream)
+        for _ in range(args.array_steps):
+            graph.launch(stream)
+        z.record(stream)
+        stream.synchronize()
+        wall = time.perf_counter() - t1
+    status = pipe.status()
+    if status:
+        raise RuntimeError("device status word %#x" % status)
+    ms = a.elapsed_time(z) / args.array_steps
+    dl0 = np.array([c.dl0_bytes for c in aw.pool.cams], np.int64)
+    ev = rta.records(evt, rta.EVENT_DTYPE)
+    n_evt, n_tel = args.array_events, len(ty)
+    r = {"array_events_per_s": n_evt / (wall / args.array_steps), "camera_events_per_s": n_tel / (wall / args.array_steps),
+         "dl0_GBps": float(dl0[ty].sum()) / (wall / args.array_steps) / 1e9, "ms_per_step": wall / args.array_steps * 1e3,
+         "gpu_ms_per_step": ms, "array_events": n_evt, "telescopes": n_tel, "mean_multiplicity": n_tel / n_evt,
+         "stereo_valid_fraction": float(np.mean((ev["flags"] & rta.EVT_STEREO_INVALID) == 0)),
+         "pool_array_events": args.array_pool, "pool_GB": aw.pool.blob.nbytes / 1e9,
+         "schedule": list(best), "steps": args.array_steps, "graph": True}
+    log("array batch: %s (%.1f s)" % (r, time.time() - t0))
+    del graph, blob_d, b, tel, evt, tb
+    torch.cuda.empty_cache()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--pool", type=int, default=3000, help="unique camera events resident in HBM")
+    ap.add_argument("--pool", type=int, default=24000,
+                    help="unique camera events resident in HBM (17 GB: far beyond the 256 MB last-level cache)")
     ap.add_argument("--events", type=int, default=1_000_000, help="camera events per step")
     ap.add_argument("--schedule", type=str, default="",
                     help="pix_per_lane,waves_per_wg,wg_per_cu,chunk (default: autotune before timing)")
@@ -107,6 +191,11 @@ def main():
                     help="array events (1:1:8 mix, network attached) paced from pinned host at --rate GB/s "
                          "for per-event latency (0: skip)")
     ap.add_argument("--rate", type=float, default=8.0, help="paced DL0 rate for the latency run, GB/s")
+    ap.add_argument("--array-events", type=int, default=200_000,
+                    help="array events per step of the batched array-event run with stereo (0: skip)")
+    ap.add_argument("--array-pool", type=int, default=1000,
+                    help="rendered array events resident in HBM for the batched run (~21k telescopes, ~15 GB)")
+    ap.add_argument("--array-steps", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, run a plain 1 GiB elementwise copy kernel twice (reads and writes "
                          "exactly 2^30 bytes each) to calibrate HBM byte counters")
@@ -184,6 +273,8 @@ def main():
     alg_bytes = int(per_hg[ty].sum() + (rec["n_lowgain"].astype(np.int64) * samp[ty] * 2).sum() + n * (64 + 12))
     dl0_bytes = int(dl0[ty].sum())
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    sched = list(pipe.schedule())
+    traffic = measured_traffic(sched, pool.n, n)
     out = {
         "metric": "camera-events/s & input GB/s (calib+clean+Hillas), % of HBM peak",
         "value": n / (ms_step * 1e-3),
@@ -205,35 +296,41 @@ def main():
                         "fused calibrate->clean->Hillas, graph replay" % (n, pool.n, pool.blob.nbytes / 1e9),
             "camera_events_per_step": n,
             "pool_events": pool.n,
-            "schedule": list(pipe.schedule()),
+            "schedule": sched,
             "autotune": tune_info,
             "graph": graph is not None,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_fused",
+            "kernel": "k_fused_grid" if sched[2] == 0 else "k_fused",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch",
             "alg_bytes_per_launch": alg_bytes,
+            "sources": sources_digest(),
             "kernel_ms": kern_ms,
         },
     }
+    # free the throughput pool before the optional runs
+    del graph, blob_d, b, tel
+    torch.cuda.empty_cache()
     if args.stream_chunks > 0:
         from paper_1307_6489_amd import stream as st
         t0 = time.time()
         hpool = W.c1_pool(args.stream_pool, seed=6)
         pinned = st.PinnedPool(hpool, 4 << 30)
-        del hpool, blob_d, b, tel
-        torch.cuda.empty_cache()
+        del hpool
         r = st.stream(pipe, pinned, args.stream_chunks, dev)
         r.update(st.copy_bandwidth(1 << 30, dev))
         r["pinned_pool_GB"] = pinned.host.numel() * 2 / 1e9
         out["pinned_stream"] = r
         log("pinned stream: %s (%.1f s)" % (r, time.time() - t0))
         del pinned
+    if args.array_events > 0:
+        out["array_batch"] = array_batch_run(args, dev, stream)
     if args.latency_events > 0:
         args.latency_schedule = pipe.schedule()
         out["array_latency"] = latency_run(args, dev)

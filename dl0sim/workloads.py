@@ -114,3 +114,21 @@ def array_events(n_evt: int, seed: int = 2, cams=None, weights=C1_WEIGHTS, mult=
     pool_idx[order] = np.arange(n_tel)
     return ArrayWorkload(pool, ad.evt_tel_off, ad.tel_type.astype(np.int32), pool.pool_off[pool_idx], pool_idx,
                          ad.src_nominal)
+
+
+def replicate_array_events(aw: ArrayWorkload, n_evt: int, seed: int):
+    """Descriptors of ``n_evt`` array events that cycle through the rendered
+    array events of ``aw`` (each pass a new seeded permutation), so a batch of
+    any size references a fixed device pool.  Returns (evt_tel_off int64
+    [n_evt+1], tel_type int32, tel_off int64, source array event index)."""
+    rng = np.random.default_rng(seed)
+    n_src = len(aw.evt_tel_off) - 1
+    src = np.concatenate([rng.permutation(n_src) for _ in range((n_evt + n_src - 1) // max(n_src, 1))])[:n_evt]
+    lo = aw.evt_tel_off[src]
+    mult = aw.evt_tel_off[src + 1] - lo
+    evt_tel_off = np.zeros(n_evt + 1, np.int64)
+    evt_tel_off[1:] = np.cumsum(mult)
+    # telescope k of output event e is telescope lo[e] + (k - evt_tel_off[e]) of the pool event
+    rel = np.arange(evt_tel_off[-1], dtype=np.int64) - np.repeat(evt_tel_off[:-1], mult)
+    tel_src = np.repeat(lo, mult) + rel
+    return evt_tel_off, aw.tel_type[tel_src].astype(np.int32), aw.tel_off[tel_src].astype(np.int64), src

@@ -53,6 +53,12 @@ __device__ __forceinline__ uint32_t pkmax16(uint32_t a, uint32_t b) {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
+// Cache-policy bits of the trace loads (bit 1 = non-temporal: every trace
+// byte is read once, so the L2 should not keep it).
+#ifndef RTA_TRACE_CPOL
+#define RTA_TRACE_CPOL 2
+#endif
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t event_rsrc(const uint16_t* base, int64_t elems) {
   // word 3 = 0x00020000: raw 32-bit data format, bounds-checked against num_records
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(base), 0, (int)(elems * 2), 0x00020000);
@@ -61,13 +67,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t event_rsrc(const uint16_t* bas
 template <int ND>
 __device__ __forceinline__ void load_slice(uint32_t (&d)[ND], __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   if constexpr (ND == 4) {
-    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, RTA_TRACE_CPOL);
     d[0] = v[0]; d[1] = v[1]; d[2] = v[2]; d[3] = v[3];
   } else if constexpr (ND == 2) {
-    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, RTA_TRACE_CPOL);
     d[0] = v[0]; d[1] = v[1];
   } else {
-    d[0] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+    d[0] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, RTA_TRACE_CPOL);
   }
 }
 

@@ -37,7 +37,7 @@ def init_params(seed):
     return np.concatenate(parts).astype(np.float32)
 
 
-def image_features(cam, n, seed, dev, chunk=50_000, first_event=0):
+def image_features(cam, n, seed, dev, chunk=50_000, first_event=0, log=None):
     """Generate n charge images and reduce them on the GPU to Hillas records
     and network features.  Returns dict of numpy arrays."""
     import torch
@@ -59,6 +59,8 @@ def image_features(cam, n, seed, dev, chunk=50_000, first_event=0):
         recs.append(rta.records(rec))
         labels.append((sh["kind"] == 1).astype(np.float32))
         energies.append(np.log10(sh["energy_tev"]).astype(np.float32))
+        if log:
+            log("images %d / %d (seed %d)" % (c0 + m, n, seed))
     return {"x": np.concatenate(feats), "rec": np.concatenate(recs), "label": np.concatenate(labels),
             "log10e": np.concatenate(energies)}
 
@@ -171,10 +173,11 @@ def main():
     dev = torch.device("cuda:0")
     cam = dl0sim.camera_c0()
     t0 = time.time()
-    tr = image_features(cam, args.train, 3, dev)
-    te = image_features(cam, args.test, 4, dev)
+    say = lambda s: print(s, flush=True)
+    tr = image_features(cam, args.train, 3, dev, log=say)
+    te = image_features(cam, args.test, 4, dev, log=say)
     print("features in %.1f s" % (time.time() - t0), flush=True)
-    net, bc, info = train(tr, dev, epochs=args.epochs, log=lambda s: print(s, flush=True))
+    net, bc, info = train(tr, dev, epochs=args.epochs, log=say)
     res = evaluate(net, bc, te, dev)
     res.update(info)
     print(json.dumps(res), flush=True)
