@@ -161,11 +161,15 @@ typedef struct rta_pipeline_params {
   float max_cond;           /* stereo: invalid at condition number >= this (1e4) */
 } rta_pipeline_params;
 
-/* Launch schedule of the fused kernel (chosen by the autotuner). */
+/* Launch schedule of the fused kernel (chosen by the autotuner).  A new
+ * pipeline starts at {8, 4, 0, 8}, the fastest schedule measured for the
+ * mixed 1855/1764/2048-pixel dual-gain workload on MI355X. */
 typedef struct rta_schedule {
   int32_t pix_per_lane;     /* 2, 4 or 8 pixels per lane (4-, 8- or 16-byte slice loads) */
   int32_t waves_per_wg;     /* 4 or 8 (256 or 512 threads) */
-  int32_t wg_per_cu;        /* persistent workgroups per compute unit, 1..4 */
+  int32_t wg_per_cu;        /* 0: one workgroup per telescope (hardware dispatch);
+                               1..4: persistent workgroups per compute unit pulling
+                               telescopes from a device work queue */
   int32_t chunk;            /* samples per double-buffered load chunk: 8 or 16 */
 } rta_schedule;
 
@@ -208,10 +212,11 @@ rta_status rta_get_schedule(const rta_pipeline* pipe, rta_schedule* s);
 /* All schedules compiled into the library; *n receives the count. */
 rta_status rta_list_schedules(rta_schedule* out, int32_t cap, int32_t* n);
 
-/* The fused path: one persistent kernel runs calibration -> cleaning ->
- * Hillas for every telescope of the batch (dynamic work queue), then (if
- * do_stereo) one pass per array event computes stereo, network scores and
- * the event record.  tel_out: [n_tel]; evt_out: [n_evt] (NULLABLE when
+/* The fused path: one kernel runs calibration -> cleaning -> Hillas for
+ * every telescope of the batch (one workgroup per telescope, or persistent
+ * workgroups on a dynamic work queue, per the schedule), then (if do_stereo)
+ * one pass per array event computes stereo, network scores and the event
+ * record.  tel_out: [n_tel]; evt_out: [n_evt] (NULLABLE when
  * do_stereo == 0). */
 rta_status rta_process_batch(rta_pipeline* pipe, const rta_batch* batch, rta_hillas_rec* tel_out,
                              rta_event_rec* evt_out, rta_stream stream);

@@ -302,7 +302,7 @@ rta_status rta_pipeline_create(rta_camera* const* cams, int32_t n_types, const r
   p->cams.assign(cams, cams + n_types);
   p->params = *params;
   p->window = cams[0]->dev.window;
-  p->sched = rta_schedule{8, 4, 3, 8};
+  p->sched = rta_schedule{8, 4, 0, 8};
   if (hipGetDevice(&p->device) != hipSuccess ||
       hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) {
     delete p;

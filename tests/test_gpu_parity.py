@@ -420,17 +420,21 @@ def test_fused_stereo_recovers_source(torch_dev):
 
 
 # ---------------------------------------------------------------- full size
-def test_full_size_stream_sampled(torch_dev):
+@pytest.mark.parametrize("sched", [(8, 4, 0, 8), (8, 4, 3, 8)])
+def test_full_size_stream_sampled(torch_dev, sched):
     """The throughput job (1e6 camera events of the 1:3:6 mix, streamed
-    through a device-resident pool in the default schedule) checked on 150
-    sampled telescopes against the oracle, event by event."""
+    through a device-resident pool; the benchmark's schedule and the
+    persistent form) checked on 150 sampled telescopes against the oracle,
+    event by event."""
     import torch
     pool = W.c1_pool(600, seed=1)
     n = 1_000_000
     idx, ty, off = W.stream_order(pool, n, seed=3)
-    say("full-size stream: %d telescopes over a %d-event pool (%.2f GB)" % (n, pool.n, pool.blob.nbytes / 1e9))
+    say("full-size stream: %d telescopes over a %d-event pool (%.2f GB), schedule %s"
+        % (n, pool.n, pool.blob.nbytes / 1e9, sched))
     cams = [rta.Camera.from_type(c) for c in pool.cams]
     pipe = rta.Pipeline(cams, do_stereo=False)
+    pipe.set_schedule(*sched)
     b = pipe.make_batch(to_dev(pool.blob, torch_dev), to_dev(ty, torch_dev), to_dev(off, torch_dev))
     tel, _ = pipe.alloc_outputs(b, torch_dev)
     pipe.process(b, tel)
@@ -456,3 +460,67 @@ def test_full_size_stream_sampled(torch_dev):
             assert g[k].tobytes() == g[first[e]].tobytes()
         else:
             first[e] = k
+
+
+def test_full_size_array_batch_sampled(torch_dev):
+    """The batched array-event job at full size: 2e5 array events of
+    multiplicity 2..40 (1:3:6 types) replicated from 100 rendered array
+    events, stereo on, replayed from a captured graph in the benchmark's
+    schedule.  Every replica of an array event must give byte-identical
+    telescope and event records; 20 source events are checked against the
+    oracle (Hillas per telescope, stereo on the kernel's float32 records)."""
+    import torch
+    aw = W.array_events(100, seed=2)
+    eo, ty, off, src = W.replicate_array_events(aw, 200_000, seed=9)
+    say("full-size array batch: 200000 array events, %d telescopes, pool %.2f GB"
+        % (len(ty), aw.pool.blob.nbytes / 1e9))
+    cams = aw.pool.cams
+    pipe = rta.Pipeline([rta.Camera.from_type(c) for c in cams], do_stereo=True)
+    pipe.set_schedule(8, 4, 0, 8)
+    b = pipe.make_batch(to_dev(aw.pool.blob, torch_dev), to_dev(ty, torch_dev), to_dev(off, torch_dev),
+                        to_dev(eo, torch_dev))
+    tel, evt = pipe.alloc_outputs(b, torch_dev)
+    graph = pipe.capture(b, tel, evt)
+    for _ in range(2):
+        graph.launch(None)
+    torch.cuda.synchronize()
+    assert pipe.status() == 0
+    g = rta.records(tel)
+    ev = rta.records(evt, rta.EVENT_DTYPE)
+    # replicas agree byte for byte
+    first = {}
+    for e in range(len(src)):
+        s0 = src[e]
+        if s0 not in first:
+            first[s0] = e
+            continue
+        f = first[s0]
+        assert ev[e].tobytes() == ev[f].tobytes()
+        assert g[eo[e]:eo[e + 1]].tobytes() == g[eo[f]:eo[f + 1]].tobytes()
+    # oracle on 20 source events (first replica of each)
+    ocs = [oracle.Camera.from_type(c) for c in cams]
+    focal = np.array([c.focal_m for c in cams])
+    rng = np.random.default_rng(12)
+    n_stereo = 0
+    for s0 in rng.choice(len(aw.evt_tel_off) - 1, 20, replace=False):
+        e = first[s0]
+        lo, hi = eo[e], eo[e + 1]
+        for k in range(lo, hi):
+            t_, o_ = ty[k], off[k]
+            p, m, h = ocs[t_].reconstruct(aw.pool.blob[o_:o_ + cams[t_].event_elems])
+            mm = par.hillas_mismatches(g[k], h, cams[t_].geom.x, cams[t_].geom.y, p["q"], p["t"], m)
+            assert not mm, (e, k, mm)
+        r = g[lo:hi]
+        valid = (r["flags"] & rta.FLAG_HILLAS_INVALID) == 0
+        f = np.asarray(focal[ty[lo:hi]], np.float32).astype(np.float64)
+        dx, dy, cond, used, flags = oracle.stereo(r["size"], r["cog_x"], r["cog_y"], r["length"], r["width"],
+                                                  r["psi"], valid.astype(np.int32), f)
+        assert ev["n_tel"][e] == hi - lo and ev["n_used"][e] == used
+        if not 0.98e4 < cond < 1.02e4:
+            assert (ev["flags"][e] & rta.EVT_STEREO_INVALID) == flags
+        if flags == 0 and not (ev["flags"][e] & rta.EVT_STEREO_INVALID):
+            c_max = float(np.max(np.hypot(r["cog_x"], r["cog_y"]) / f))
+            bad, d, lim = par.stereo_mismatch((ev["dir_x"][e], ev["dir_y"][e]), (dx, dy), cond, c_max)
+            assert not bad, (e, d, lim, cond)
+            n_stereo += 1
+    assert n_stereo >= 15
