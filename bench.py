@@ -3,7 +3,7 @@
 Workload (the mixed-camera throughput configuration): dual-gain uint16 traces
 of 1855-px x 40-sample, 1764-px x 25-sample and 2048-px x 128-sample cameras
 in ratio 1:3:6, plain ellipse images.  A seeded pool of unique camera events
-(default 24000, about 17 GB: re-reads of a pool a few times the size of the
+(default 45000, about 32 GB: re-reads of a pool a few times the size of the
 256 MB last-level cache still hit it measurably) is made resident in HBM; one step is one pass of calibration -> cleaning ->
 Hillas over 1e6 camera events streamed through the pool in a seeded random
 order, replayed from a captured HIP graph.  Inputs are resident before the
@@ -37,8 +37,8 @@ HBM_PEAK_GBPS = 8000.0
 # otherwise.
 COUNTER_SOURCES = ("paper_1307_6489_amd/csrc/reco.hip", "paper_1307_6489_amd/csrc/rta_internal.h")
 MEASURED_TRAFFIC = {
-    "sources": "2669cee41d5904c0", "schedule": (8, 4, 0, 8), "pool_events": 24000, "events": 1_000_000,
-    "fetch_kib": 180694329.5, "fetch_factor": 2.0, "write_kib": 62500.02, "write_factor": 1.0,
+    "sources": "2669cee41d5904c0", "schedule": (8, 4, 0, 8), "pool_events": 45000, "events": 1_000_000,
+    "fetch_kib": 180722095.3, "fetch_factor": 2.0, "write_kib": 62500.02, "write_factor": 1.0,
 }
 
 
@@ -63,28 +63,47 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pool, ty, off, target_s=10.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pool, ty, off, target_s=10.0, single_s=3.0):
     """The oracle as it stands, on host cores, over a bounded sample of the
-    same descriptor stream (time-bounded: chunks of 1000 events until about
-    target_s seconds of wall time)."""
+    same descriptor stream (time-bounded: chunks of events until about
+    target_s seconds of wall time with all threads, then single_s seconds on
+    one thread)."""
     import oracle
     ocs = [oracle.Camera.from_type(c) for c in pool.cams]
     threads = max(1, min(16, os.cpu_count() or 1))
-    done, t_used, k = 0, 0.0, 0
     per = np.array([c.dl0_bytes for c in pool.cams], np.int64)
-    nbytes = 0
-    while t_used < target_s and k < len(ty):
-        sl = slice(k, min(k + 1000, len(ty)))
-        t0 = time.perf_counter()
-        oracle.reconstruct_batch(ocs, ty[sl], pool.blob, off[sl], n_threads=threads)
-        t_used += time.perf_counter() - t0
-        done += sl.stop - sl.start
-        nbytes += int(per[ty[sl]].sum())
-        k = sl.stop
+
+    def run(n_threads, budget, chunk):
+        done, t_used, k, nbytes = 0, 0.0, 0, 0
+        while t_used < budget and k < len(ty):
+            sl = slice(k, min(k + chunk, len(ty)))
+            t0 = time.perf_counter()
+            oracle.reconstruct_batch(ocs, ty[sl], pool.blob, off[sl], n_threads=n_threads)
+            t_used += time.perf_counter() - t0
+            done += sl.stop - sl.start
+            nbytes += int(per[ty[sl]].sum())
+            k = sl.stop
+        return done, t_used, nbytes
+
+    done, t_used, nbytes = run(threads, target_s, 1000)
+    d1, t1, b1 = run(1, single_s, 50)
     return {"value": done / t_used, "unit": "camera-events/s", "cores": threads, "kind": "oracle",
             "sample": "first %d camera events of the same stream order (C++ FP64 oracle, %d threads, "
                       "%.1f s wall)" % (done, threads, t_used),
-            "input_GBps": nbytes / t_used / 1e9}
+            "input_GBps": nbytes / t_used / 1e9,
+            "single_thread": {"value": d1 / t1, "events": d1, "seconds": t1, "input_GBps": b1 / t1 / 1e9},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def latency_run(args, dev):
@@ -173,8 +192,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--pool", type=int, default=24000,
-                    help="unique camera events resident in HBM (17 GB: far beyond the 256 MB last-level cache)")
+    ap.add_argument("--pool", type=int, default=45000,
+                    help="unique camera events resident in HBM (32 GB: far beyond the 256 MB last-level cache)")
     ap.add_argument("--events", type=int, default=1_000_000, help="camera events per step")
     ap.add_argument("--schedule", type=str, default="",
                     help="pix_per_lane,waves_per_wg,wg_per_cu,chunk (default: autotune before timing)")
