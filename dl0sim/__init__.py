@@ -181,12 +181,15 @@ class CameraType:
     ped_jitter: float = 0.0        # optional per-pixel pedestal spread (ADC, uniform +-)
     gain_jitter: float = 0.0       # optional per-pixel relative gain spread (uniform +-)
     table_seed: int = 0
+    fixed_start: int = -1          # fixed-window readout start; -1: (n_samp - window) // 2
     geom: Geometry = field(default=None, repr=False)
     adc_per_pe: np.ndarray = field(default=None, repr=False)   # float32 [G][N]
     base_ped: np.ndarray = field(default=None, repr=False)     # float32 [G][N]
     ped: np.ndarray = field(default=None, repr=False)          # float32 [G][N] per-sample pedestal table
 
     def __post_init__(self):
+        if self.fixed_start < 0:
+            self.fixed_start = (self.n_samp - self.window) // 2
         if self.geom is None:
             self.geom = hex_geometry(self.n_pix, self.pitch)
         G, N = self.n_gain, self.n_pix

@@ -11,8 +11,19 @@
  *   Gain selection   a pixel uses its low-gain trace iff its highest raw
  *                    high-gain sample is >= hg_switch_adc (dual-gain only).
  *   Extraction       W(s) = sum_{k<w} x[s+k] on the selected gain,
- *                    s* = the earliest maximiser over s in [0, T-w],
  *                    S = W(s*); peak = s* + earliest argmax of x[s*..s*+w-1].
+ *                    The window start s* comes from the signal extractor
+ *                    (the paper's Section 5 plans several extraction
+ *                    algorithms on the GPU; three are provided):
+ *                    RTA_EXTRACT_SLIDING: the earliest maximiser of W(s) over
+ *                      s in [0, T-w] (the default);
+ *                    RTA_EXTRACT_FIXED: s* = the camera's fixed_start for
+ *                      every pixel; the gain decision looks only at the
+ *                      high-gain samples fixed_start .. fixed_start+w-1, and
+ *                      nothing outside the window is read;
+ *                    RTA_EXTRACT_GLOBAL_PEAK: s* = the earliest maximiser of
+ *                      the camera sum over pixels of the raw high-gain W(s),
+ *                      common to every pixel of the event.
  *   Calibration      P = nearest-even(256 * ped) (Q8 fixed point),
  *                    D = 256*S - w*P,  q = D / (256 * adc_per_pe)  [p.e.],
  *                    Nt = sum_{k<w} k*(256*x[s*+k] - P),
@@ -71,6 +82,11 @@ extern "C" {
 #define RTA_MAX_SAMP 255      /* largest trace length */
 #define RTA_MAX_TYPES 8       /* camera types per pipeline */
 
+/* signal extractors (window placement, see Extraction above) */
+#define RTA_EXTRACT_SLIDING 0
+#define RTA_EXTRACT_FIXED 1
+#define RTA_EXTRACT_GLOBAL_PEAK 2
+
 typedef enum rta_status {
   RTA_OK = 0,
   RTA_E_INVALID_ARG = 1,  /* null handle/pointer, negative count, misalignment */
@@ -118,10 +134,11 @@ typedef struct rta_camera_desc {
   float focal_m;          /* focal length (stereo nominal frame) */
   float t_pic;            /* picture level, p.e. */
   float t_bnd;            /* boundary level, p.e., <= t_pic */
+  int32_t fixed_start;    /* first sample of the fixed window, 0..n_samp-window */
 } rta_camera_desc;
 
 typedef struct rta_camera_info {
-  int32_t n_pix, n_pix_pad, n_samp, n_gain, window, pad_;
+  int32_t n_pix, n_pix_pad, n_samp, n_gain, window, fixed_start;
   int64_t event_elems;    /* uint16 elements per camera event: G*T*Npad */
 } rta_camera_info;
 
@@ -156,7 +173,8 @@ typedef struct rta_batch {
 
 typedef struct rta_pipeline_params {
   int32_t do_stereo;        /* 1: per-event stereo + event records */
-  int32_t pad_;
+  int32_t extractor;        /* RTA_EXTRACT_*; extractors other than SLIDING always
+                               run one workgroup per telescope (wg_per_cu ignored) */
   float max_width_ratio;    /* stereo: drop images with width/length above (0.9) */
   float max_cond;           /* stereo: invalid at condition number >= this (1e4) */
 } rta_pipeline_params;
@@ -186,11 +204,16 @@ rta_status rta_camera_create(const rta_camera_desc* desc, rta_camera** out);
 rta_status rta_camera_destroy(rta_camera* cam);
 rta_status rta_camera_get_info(const rta_camera* cam, rta_camera_info* info);
 
-/* Calibration + extraction of n_evt camera events of one type.
- * traces: [n_evt][G][T][Npad].  Outputs [n_evt][N], each NULLABLE:
- * S, D (int32), sstar, peak, gain (uint8), q (p.e.), t (samples) as float. */
+/* Calibration + extraction of n_evt camera events of one type with the
+ * sliding-window extractor.  traces: [n_evt][G][T][Npad].  Outputs
+ * [n_evt][N], each NULLABLE: S, D (int32), sstar, peak, gain (uint8),
+ * q (p.e.), t (samples) as float. */
 rta_status rta_calibrate(const rta_camera* cam, const uint16_t* traces, int64_t n_evt, int32_t* S, int32_t* D,
                          uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q, float* t, rta_stream stream);
+/* The same with any extractor (RTA_EXTRACT_*; RTA_E_INVALID_ARG otherwise). */
+rta_status rta_calibrate_ex(const rta_camera* cam, int32_t extractor, const uint16_t* traces, int64_t n_evt,
+                            int32_t* S, int32_t* D, uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q,
+                            float* t, rta_stream stream);
 
 /* Two-level tailcut of n_evt events.  D, gain: [n_evt][N] (gain NULLABLE =
  * all high gain).  mask: [n_evt][N] 0/1. */

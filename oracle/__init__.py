@@ -35,6 +35,11 @@ TIME_INVALID = 2
 LOW_GAIN = 4
 STEREO_INVALID = 1
 
+# signal extractors (window placement)
+EX_SLIDING = 0
+EX_FIXED = 1
+EX_GLOBAL_PEAK = 2
+
 
 def build(force: bool = True) -> str:
     """Compile ``oracle.c`` with gcc (plain -O2, no vector intrinsics)."""
@@ -49,7 +54,8 @@ class OracleCam(ctypes.Structure):
     _fields_ = [
         ("n_pix", ctypes.c_int32), ("n_pix_pad", ctypes.c_int32), ("n_samp", ctypes.c_int32),
         ("n_gain", ctypes.c_int32), ("window", ctypes.c_int32), ("hg_switch", ctypes.c_int32),
-        ("max_nbr", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("max_nbr", ctypes.c_int32), ("extractor", ctypes.c_int32),
+        ("fixed_start", ctypes.c_int32), ("pad_", ctypes.c_int32),
         ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("ped", ctypes.c_void_p), ("a", ctypes.c_void_p),
         ("nbr", ctypes.c_void_p), ("t_pic", ctypes.c_double), ("t_bnd", ctypes.c_double),
         ("focal", ctypes.c_double),
@@ -112,7 +118,7 @@ class Camera:
     neighbour lists by the O(N^2) distance test with tolerance 1.4 x pitch."""
 
     def __init__(self, n_pix, n_samp, n_gain, x, y, ped, adc_per_pe, pitch, window=4, hg_switch=4000,
-                 t_pic=10.0, t_bnd=5.0, focal=1.0):
+                 t_pic=10.0, t_bnd=5.0, focal=1.0, extractor=EX_SLIDING, fixed_start=None):
         self.n_pix, self.n_samp, self.n_gain = int(n_pix), int(n_samp), int(n_gain)
         self.n_pix_pad = (self.n_pix + 7) // 8 * 8
         self.window, self.hg_switch = int(window), int(hg_switch)
@@ -122,14 +128,21 @@ class Camera:
         self.a = np.ascontiguousarray(np.asarray(adc_per_pe, np.float32).reshape(self.n_gain, self.n_pix))
         self.nbr = neighbours(self.x, self.y, 1.4 * pitch)
         self.t_pic, self.t_bnd, self.focal = float(t_pic), float(t_bnd), float(focal)
+        self.extractor = int(extractor)
+        self.fixed_start = (self.n_samp - self.window) // 2 if fixed_start is None else int(fixed_start)
+        if self.extractor not in (EX_SLIDING, EX_FIXED, EX_GLOBAL_PEAK):
+            raise ValueError("unknown extractor")
+        if not 0 <= self.fixed_start <= self.n_samp - self.window:
+            raise ValueError("fixed window outside the trace")
         self.c = OracleCam(self.n_pix, self.n_pix_pad, self.n_samp, self.n_gain, self.window, self.hg_switch,
-                           self.nbr.shape[1], 0, _p(self.x), _p(self.y), _p(self.ped), _p(self.a),
-                           _p(self.nbr), self.t_pic, self.t_bnd, self.focal)
+                           self.nbr.shape[1], self.extractor, self.fixed_start, 0, _p(self.x), _p(self.y),
+                           _p(self.ped), _p(self.a), _p(self.nbr), self.t_pic, self.t_bnd, self.focal)
 
     @classmethod
-    def from_type(cls, cam, t_pic=10.0, t_bnd=5.0):
+    def from_type(cls, cam, t_pic=10.0, t_bnd=5.0, extractor=EX_SLIDING):
         return cls(cam.n_pix, cam.n_samp, cam.n_gain, cam.geom.x, cam.geom.y, cam.ped, cam.adc_per_pe,
-                   cam.pitch, cam.window, cam.hg_switch_adc, t_pic, t_bnd, cam.focal_m)
+                   cam.pitch, cam.window, cam.hg_switch_adc, t_pic, t_bnd, cam.focal_m, extractor,
+                   cam.fixed_start)
 
     @property
     def event_elems(self):

@@ -11,7 +11,17 @@
  *
  *   gain selection   low gain iff the highest raw high-gain sample >= switch
  *   window sum       W(s) = sum_{k<w} x[s+k] for every start s in [0, T-w],
- *                    summed directly (no running sum); s* = first maximiser
+ *                    summed directly (no running sum)
+ *   window start s*  by the camera's signal extractor (the paper's Section 5
+ *                    mentions several extraction algorithms; three are here):
+ *                    sliding      first maximiser of W(s) on the pixel's
+ *                                 selected gain
+ *                    fixed        s0, the same for every pixel; the gain
+ *                                 decision looks only at the high-gain
+ *                                 samples s0 .. s0+w-1
+ *                    global peak  first maximiser of C(s) = the sum over all
+ *                                 pixels of the raw high-gain W(s), the same
+ *                                 for every pixel of the event
  *   pedestal (Q8)    P = nearest-even(256 * ped);  D = 256 * W(s*) - w * P
  *   time numerator   Nt = sum_{k<w} k * (256 * x[s*+k] - P)
  *   charge / time    q = D / (256 * a)  p.e.;  t = s* + Nt / D  (D > 0),
@@ -38,9 +48,12 @@
 
 #define OR_PI 3.14159265358979323846
 
+enum { OR_EX_SLIDING = 0, OR_EX_FIXED = 1, OR_EX_GLOBAL_PEAK = 2 };
+
 typedef struct oracle_cam {
   int32_t n_pix, n_pix_pad, n_samp, n_gain;
-  int32_t window, hg_switch, max_nbr, pad_;
+  int32_t window, hg_switch, max_nbr, extractor;
+  int32_t fixed_start, pad_;
   const float* x;        /* [N] m */
   const float* y;        /* [N] m */
   const float* ped;      /* [G][N] per-sample pedestal, ADC */
@@ -100,25 +113,45 @@ static int64_t q8_threshold(float a, double level) { return (int64_t)ceil(256.0 
 /* ------------------------------------------------------------------ */
 void oracle_calibrate_event(const oracle_cam* cam, const uint16_t* ev, oracle_pix* out) {
   const int N = cam->n_pix, Np = cam->n_pix_pad, T = cam->n_samp, G = cam->n_gain, w = cam->window;
+  const int ex = cam->extractor, s0 = cam->fixed_start;
+  /* global peak: the camera-summed raw high-gain window, first maximiser */
+  int sglob = 0;
+  if (ex == OR_EX_GLOBAL_PEAK) {
+    int64_t cbest = -1;
+    for (int s = 0; s + w <= T; ++s) {
+      int64_t C = 0;
+      for (int j = 0; j < N; ++j)
+        for (int k = 0; k < w; ++k) C += ev[(int64_t)(s + k) * Np + j];
+      if (C > cbest) { cbest = C; sglob = s; }
+    }
+  }
   for (int i = 0; i < N; ++i) {
-    /* gain selection on the raw high-gain trace */
+    /* gain selection on the raw high-gain trace (the fixed window looks
+       only inside the window) */
     int g = 0;
     if (G == 2) {
+      const int k_lo = ex == OR_EX_FIXED ? s0 : 0, k_hi = ex == OR_EX_FIXED ? s0 + w : T;
       int64_t hmax = 0;
-      for (int k = 0; k < T; ++k) {
+      for (int k = k_lo; k < k_hi; ++k) {
         int64_t v = ev[(int64_t)k * Np + i];
         if (v > hmax) hmax = v;
       }
       if (hmax >= cam->hg_switch) g = 1;
     }
     const uint16_t* tr = ev + (int64_t)g * T * Np + i;   /* sample k at tr[k * Np] */
-    /* every window summed directly; the first maximiser wins */
     int64_t best = -1;
     int sbest = 0;
-    for (int s = 0; s + w <= T; ++s) {
-      int64_t W = 0;
-      for (int k = 0; k < w; ++k) W += tr[(int64_t)(s + k) * Np];
-      if (W > best) { best = W; sbest = s; }
+    if (ex == OR_EX_SLIDING) {
+      /* every window summed directly; the first maximiser wins */
+      for (int s = 0; s + w <= T; ++s) {
+        int64_t W = 0;
+        for (int k = 0; k < w; ++k) W += tr[(int64_t)(s + k) * Np];
+        if (W > best) { best = W; sbest = s; }
+      }
+    } else {
+      sbest = ex == OR_EX_FIXED ? s0 : sglob;
+      best = 0;
+      for (int k = 0; k < w; ++k) best += tr[(int64_t)(sbest + k) * Np];
     }
     int64_t P = q8_pedestal(cam->ped[g * N + i]);
     int64_t D = 256 * best - (int64_t)w * P;

@@ -19,6 +19,9 @@ LIB_PATH = os.path.join(_PKG, "librta.so")
 RTA_OK = 0
 STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "unsupported shape", 3: "HIP runtime error",
                 4: "out of memory", 5: "unsupported option"}
+EXTRACT_SLIDING = 0       # per pixel: earliest maximiser of the window sum
+EXTRACT_FIXED = 1         # every pixel: the camera's fixed window start
+EXTRACT_GLOBAL_PEAK = 2   # every pixel: earliest maximiser of the camera-summed window
 FLAG_HILLAS_INVALID = 0x1
 FLAG_TIME_INVALID = 0x2
 FLAG_LOW_GAIN = 0x4
@@ -45,12 +48,12 @@ class CameraDesc(ctypes.Structure):
                 ("window", ctypes.c_int32), ("hg_switch_adc", ctypes.c_int32), ("max_nbr", ctypes.c_int32),
                 ("pix_x", ctypes.c_void_p), ("pix_y", ctypes.c_void_p), ("nbr", ctypes.c_void_p),
                 ("ped", ctypes.c_void_p), ("adc_per_pe", ctypes.c_void_p), ("focal_m", ctypes.c_float),
-                ("t_pic", ctypes.c_float), ("t_bnd", ctypes.c_float)]
+                ("t_pic", ctypes.c_float), ("t_bnd", ctypes.c_float), ("fixed_start", ctypes.c_int32)]
 
 
 class CameraInfo(ctypes.Structure):
     _fields_ = [("n_pix", ctypes.c_int32), ("n_pix_pad", ctypes.c_int32), ("n_samp", ctypes.c_int32),
-                ("n_gain", ctypes.c_int32), ("window", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("n_gain", ctypes.c_int32), ("window", ctypes.c_int32), ("fixed_start", ctypes.c_int32),
                 ("event_elems", ctypes.c_int64)]
 
 
@@ -61,7 +64,7 @@ class Batch(ctypes.Structure):
 
 
 class PipelineParams(ctypes.Structure):
-    _fields_ = [("do_stereo", ctypes.c_int32), ("pad_", ctypes.c_int32), ("max_width_ratio", ctypes.c_float),
+    _fields_ = [("do_stereo", ctypes.c_int32), ("extractor", ctypes.c_int32), ("max_width_ratio", ctypes.c_float),
                 ("max_cond", ctypes.c_float)]
 
 
@@ -91,6 +94,7 @@ SYMBOLS = {
     "rta_camera_destroy": ([_vp], ctypes.c_int),
     "rta_camera_get_info": ([_vp, _vp], ctypes.c_int),
     "rta_calibrate": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "rta_calibrate_ex": ([_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "rta_clean": ([_vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_hillas": ([_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_pipeline_create": ([_vp, _i32, _vp, _vp], ctypes.c_int),
@@ -202,7 +206,7 @@ class Camera:
     thresholds, neighbour table)."""
 
     def __init__(self, n_pix, n_samp, n_gain, x, y, nbr, ped, adc_per_pe, focal_m, window=4, hg_switch_adc=4000,
-                 t_pic=10.0, t_bnd=5.0):
+                 t_pic=10.0, t_bnd=5.0, fixed_start=None):
         self._keep = dict(x=np.ascontiguousarray(x, np.float32), y=np.ascontiguousarray(y, np.float32),
                           nbr=np.ascontiguousarray(nbr, np.int32),
                           ped=np.ascontiguousarray(ped, np.float32).reshape(n_gain, n_pix),
@@ -210,7 +214,7 @@ class Camera:
         k = self._keep
         d = CameraDesc(n_pix, n_samp, n_gain, window, hg_switch_adc, k["nbr"].shape[1] if k["nbr"].ndim == 2 else 0,
                        _ptr(k["x"]), _ptr(k["y"]), _ptr(k["nbr"]), _ptr(k["ped"]), _ptr(k["a"]), focal_m, t_pic,
-                       t_bnd)
+                       t_bnd, (n_samp - window) // 2 if fixed_start is None else fixed_start)
         h = ctypes.c_void_p()
         _check(lib().rta_camera_create(ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
@@ -218,14 +222,16 @@ class Camera:
         _check(lib().rta_camera_get_info(h, ctypes.byref(info)))
         self.n_pix, self.n_pix_pad, self.n_samp = info.n_pix, info.n_pix_pad, info.n_samp
         self.n_gain, self.window, self.event_elems = info.n_gain, info.window, info.event_elems
+        self.fixed_start = info.fixed_start
         self.focal_m = focal_m
 
     @classmethod
     def from_type(cls, ct, t_pic=10.0, t_bnd=5.0):
         """From any camera-type object with n_pix, n_samp, n_gain, geom.{x,y,nbr},
-        ped, adc_per_pe, focal_m, window and hg_switch_adc attributes."""
+        ped, adc_per_pe, focal_m, window, hg_switch_adc and (optionally)
+        fixed_start attributes."""
         return cls(ct.n_pix, ct.n_samp, ct.n_gain, ct.geom.x, ct.geom.y, ct.geom.nbr, ct.ped, ct.adc_per_pe,
-                   ct.focal_m, ct.window, ct.hg_switch_adc, t_pic, t_bnd)
+                   ct.focal_m, ct.window, ct.hg_switch_adc, t_pic, t_bnd, getattr(ct, "fixed_start", None))
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -241,8 +247,10 @@ class Camera:
         return traces.numel() // self.event_elems
 
 
-def calibrate(cam: Camera, traces, stream=None, outputs=("S", "D", "sstar", "peak", "gain", "q", "t")):
-    """Per-pixel calibration of every event of ``traces`` (uint16 [E][G][T][Npad])."""
+def calibrate(cam: Camera, traces, stream=None, outputs=("S", "D", "sstar", "peak", "gain", "q", "t"),
+              extractor=None):
+    """Per-pixel calibration of every event of ``traces`` (uint16 [E][G][T][Npad]);
+    ``extractor`` one of EXTRACT_* (default: the sliding window)."""
     import torch
     E = cam._n_evt(traces)
     dev = traces.device
@@ -250,8 +258,12 @@ def calibrate(cam: Camera, traces, stream=None, outputs=("S", "D", "sstar", "pea
           "q": torch.float32, "t": torch.float32}
     out = {k: torch.empty((E, cam.n_pix), dtype=dt[k], device=dev) for k in outputs}
     g = lambda k: _ptr(out.get(k))  # noqa: E731
-    _check(lib().rta_calibrate(cam.handle, _ptr(traces), E, g("S"), g("D"), g("sstar"), g("peak"), g("gain"),
-                               g("q"), g("t"), _stream(stream)))
+    if extractor is None:
+        _check(lib().rta_calibrate(cam.handle, _ptr(traces), E, g("S"), g("D"), g("sstar"), g("peak"), g("gain"),
+                                   g("q"), g("t"), _stream(stream)))
+    else:
+        _check(lib().rta_calibrate_ex(cam.handle, int(extractor), _ptr(traces), E, g("S"), g("D"), g("sstar"),
+                                      g("peak"), g("gain"), g("q"), g("t"), _stream(stream)))
     return out
 
 
@@ -289,10 +301,11 @@ def records(t, dtype=HILLAS_DTYPE):
 class Pipeline:
     """Fused batched path over several camera types."""
 
-    def __init__(self, cams, do_stereo=True, max_width_ratio=0.9, max_cond=1e4):
+    def __init__(self, cams, do_stereo=True, max_width_ratio=0.9, max_cond=1e4, extractor=0):
         self.cams = list(cams)
         arr = (ctypes.c_void_p * len(self.cams))(*[c.handle.value for c in self.cams])
-        p = PipelineParams(1 if do_stereo else 0, 0, max_width_ratio, max_cond)
+        p = PipelineParams(1 if do_stereo else 0, int(extractor), max_width_ratio, max_cond)
+        self.extractor = int(extractor)
         h = ctypes.c_void_p()
         _check(lib().rta_pipeline_create(arr, len(self.cams), ctypes.byref(p), ctypes.byref(h)))
         self.handle = h

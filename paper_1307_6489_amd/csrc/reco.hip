@@ -116,7 +116,7 @@ __device__ __forceinline__ DevCam uniform_cam(const DevCam& c) {
   u.hg_switch = uniform_i32(c.hg_switch);
   u.event_elems = uniform_i64(c.event_elems);
   u.focal = __int_as_float(uniform_i32(__float_as_int(c.focal)));
-  u.pad_ = 0;
+  u.fixed_start = uniform_i32(c.fixed_start);
   u.P256 = uniform_ptr(c.P256);
   u.thr_pic = uniform_ptr(c.thr_pic);
   u.thr_bnd = uniform_ptr(c.thr_bnd);
@@ -285,6 +285,209 @@ __device__ __forceinline__ uint32_t extract_group(const DevCam& c, __amdgpu_buff
   return sw;
 }
 
+// ---------------------------------------------------------------------------
+// Window placement by the other extractors.  They produce the same packed key
+// (S << 8) | (255 - s*) as the sliding window, so every later step is shared.
+// ---------------------------------------------------------------------------
+enum : int { kExSliding = RTA_EXTRACT_SLIDING, kExFixed = RTA_EXTRACT_FIXED, kExGlobal = RTA_EXTRACT_GLOBAL_PEAK };
+
+// Sums of the W samples from slice s on of every pixel of the group (one
+// load per slice) and, with TRACK_MAX, their packed per-pixel maximum.
+template <int PPL, int W, bool TRACK_MAX>
+__device__ __forceinline__ void window_at(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t sbase, uint32_t stride,
+                                          int s, uint32_t (&S)[PPL], uint32_t (&mx)[PPL / 2]) {
+  constexpr int ND = PPL / 2;
+  uint32_t d[W][ND];
+  uint32_t soff = sbase + (uint32_t)s * stride;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    load_slice<ND>(d[k], r, voff, soff);
+    soff += stride;
+  }
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) S[p] = 0;
+#pragma unroll
+  for (int h = 0; h < ND; ++h) mx[h] = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+#pragma unroll
+    for (int h = 0; h < ND; ++h) {
+      S[2 * h] += lo16(d[k][h]);
+      S[2 * h + 1] += hi16(d[k][h]);
+      if constexpr (TRACK_MAX) mx[h] = pkmax16(mx[h], d[k][h]);
+    }
+  }
+}
+
+// Keys of a group whose window start s is known; sw: pixels on low gain.
+template <int PPL, int W>
+__device__ __forceinline__ void keys_at(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t stride, int T, int s,
+                                        const uint32_t (&S_hg)[PPL], uint32_t sw, uint32_t (&key)[PPL]) {
+  uint32_t S[PPL];
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) S[p] = S_hg[p];
+  if (__ballot(sw != 0u)) {
+    uint32_t SL[PPL], unused[PPL / 2];
+    window_at<PPL, W, false>(r, voff, (uint32_t)T * stride, stride, s, SL, unused);
+#pragma unroll
+    for (int p = 0; p < PPL; ++p)
+      if ((sw >> p) & 1u) S[p] = SL[p];
+  }
+  const uint32_t low = 255u - (uint32_t)s;
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) key[p] = (S[p] << 8) | low;
+}
+
+// Fixed window: samples s0 .. s0+W-1 of every pixel, the gain decided on the
+// high-gain samples of that window; nothing else of the trace is read.
+template <int PPL, int W>
+__device__ __forceinline__ uint32_t fixed_group(const DevCam& c, __amdgpu_buffer_rsrc_t r, int pix0, int np, int T,
+                                                bool dual, uint32_t (&key)[PPL]) {
+  const uint32_t voff = (uint32_t)pix0 * 2u, stride = (uint32_t)np * 2u;
+  const int s0 = c.fixed_start;
+  uint32_t S[PPL], mx[PPL / 2];
+  window_at<PPL, W, true>(r, voff, 0u, stride, s0, S, mx);
+  uint32_t sw = 0;
+  if (dual) {
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const uint32_t m = (p & 1) ? hi16(mx[p >> 1]) : lo16(mx[p >> 1]);
+      if ((int)m >= c.hg_switch) sw |= 1u << p;
+    }
+  }
+  keys_at<PPL, W>(r, voff, stride, T, s0, S, sw, key);
+  return sw;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Global peak, first stage for one group: the wave's sum of the raw
+// high-gain samples of pixels below N, slice by slice, added into rows[k]
+// (stored on the first pass); returns the group's low-gain bits (full-trace
+// raw high-gain maximum >= switch).
+template <int PPL, int CH>
+__device__ __forceinline__ uint32_t global_rows_group(const DevCam& c, __amdgpu_buffer_rsrc_t r, int pix0, int np,
+                                                      int T, bool dual, uint32_t* rows, bool first) {
+  constexpr int ND = PPL / 2;
+  const uint32_t voff = (uint32_t)pix0 * 2u, stride = (uint32_t)np * 2u;
+  const int nv = min(max(c.n_pix - pix0, 0), PPL);
+  uint32_t msk[ND], rmax[ND];
+#pragma unroll
+  for (int h = 0; h < ND; ++h) {
+    msk[h] = (2 * h + 1 < nv) ? 0xffffffffu : (2 * h < nv ? 0x0000ffffu : 0u);
+    rmax[h] = 0;
+  }
+  const bool writer = (threadIdx.x & (kWave - 1)) == 0;
+  uint32_t A[CH][ND];
+  for (int k0 = 0; k0 < T; k0 += CH) {
+    load_chunk<PPL, CH>(A, r, voff, 0u, stride, k0);
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      if (k0 + j >= T) continue;
+      uint32_t v = 0;
+#pragma unroll
+      for (int h = 0; h < ND; ++h) {
+        const uint32_t x = A[j][h] & msk[h];
+        v += lo16(x) + hi16(x);
+        rmax[h] = pkmax16(rmax[h], x);
+      }
+      v = wave_sum_u32(v);
+      if (writer) rows[k0 + j] = first ? v : rows[k0 + j] + v;
+    }
+  }
+  uint32_t sw = 0;
+  if (dual) {
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const uint32_t m = (p & 1) ? hi16(rmax[p >> 1]) : lo16(rmax[p >> 1]);
+      if ((int)m >= c.hg_switch) sw |= 1u << p;
+    }
+  }
+  return sw;
+}
+
+// Global peak start: the earliest maximiser of C(s) = sum_{k<W} of the
+// camera-summed slices, from the per-wave partial sums rows[w * 256 + k].
+// Called by every thread of the block (contains a barrier).
+template <int NT, int W>
+__device__ __forceinline__ int global_start(const uint32_t* rows, int T, int32_t* start) {
+  constexpr int NW = NT / kWave;
+  if (threadIdx.x < kWave) {
+    uint64_t best = 0;
+    for (int s = threadIdx.x; s + W <= T; s += kWave) {
+      uint64_t C = 0;
+#pragma unroll
+      for (int k = 0; k < W; ++k)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) C += rows[w * 256 + s + k];
+      const uint64_t cand = (C << 8) | (uint64_t)(255 - s);
+      best = cand > best ? cand : best;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) {
+      const uint64_t o = __shfl_xor(best, off, kWave);
+      best = o > best ? o : best;
+    }
+    if (threadIdx.x == 0) *start = 255 - (int)(best & 255u);
+  }
+  __syncthreads();
+  return *start;
+}
+
+// Keys of every pixel of one event, group by group: fn(pix0, key, sw) for
+// each of this thread's groups.  rows / start: LDS scratch of the global
+// peak (NT/64 * 256 words, one word).
+template <int EX, int PPL, int W, int CH, int NT, class Fn>
+__device__ __forceinline__ void extract_event(const DevCam& c, __amdgpu_buffer_rsrc_t r, uint32_t* rows,
+                                              int32_t* start, Fn&& fn) {
+  const int N = c.n_pix, np = c.n_pix_pad, T = c.n_samp;
+  const bool dual = c.n_gain == 2;
+  // Uniform pass loop: every lane streams (loads past the event read 0 from
+  // the bounds-checked buffer); the callback guards its stores.
+  const int npass = (N + NT * PPL - 1) / (NT * PPL);
+  if constexpr (EX == kExSliding || EX == kExFixed) {
+    for (int ps = 0; ps < npass; ++ps) {
+      const int pix0 = (ps * NT + (int)threadIdx.x) * PPL;
+      uint32_t key[PPL];
+      uint32_t sw;
+      if constexpr (EX == kExSliding)
+        sw = extract_group<PPL, W, CH>(c, r, pix0, np, T, dual, key);
+      else
+        sw = fixed_group<PPL, W>(c, r, pix0, np, T, dual, key);
+      fn(pix0, key, sw);
+    }
+  } else {
+    constexpr int MAXP = (kMaxPix + NT * PPL - 1) / (NT * PPL);
+    uint32_t* my_rows = rows + (threadIdx.x / kWave) * 256;
+    uint32_t swp[MAXP];
+#pragma unroll
+    for (int ps = 0; ps < MAXP; ++ps) {
+      swp[ps] = 0;
+      if (ps < npass)
+        swp[ps] = global_rows_group<PPL, CH>(c, r, (ps * NT + (int)threadIdx.x) * PPL, np, T, dual, my_rows,
+                                             ps == 0);
+    }
+    __syncthreads();
+    const int s = global_start<NT, W>(rows, T, start);
+    const uint32_t stride = (uint32_t)np * 2u;
+#pragma unroll
+    for (int ps = 0; ps < MAXP; ++ps) {
+      if (ps < npass) {
+        const int pix0 = (ps * NT + (int)threadIdx.x) * PPL;
+        const uint32_t voff = (uint32_t)pix0 * 2u;
+        uint32_t S[PPL], unused[PPL / 2], key[PPL];
+        window_at<PPL, W, false>(r, voff, 0u, stride, s, S, unused);
+        keys_at<PPL, W>(r, voff, stride, T, s, S, swp[ps], key);
+        fn(pix0, key, swp[ps]);
+      }
+    }
+  }
+}
+
 // D = 256*S - w*P from the packed key.
 template <int W>
 __device__ __forceinline__ int32_t key_to_d(uint32_t key, int32_t P) {
@@ -329,9 +532,13 @@ struct TelSmem {
   uint64_t mbits[kMaxWords]; // cleaning mask, one word per 64 pixels
   int32_t wbase[kMaxWords + 1];
   uint16_t list[kMaxPix];    // slot -> pixel
-  float q[kMaxPix];          // charge per slot, p.e.
+  union {
+    float q[kMaxPix];        // charge per slot, p.e.
+    uint32_t rows[kMaxPix];  // global peak: per-wave slice sums (extraction only)
+  };
   double t[kMaxPix];         // peak time per slot, samples
   double red[16 * 8];        // cross-wave reduction scratch
+  int32_t start;             // global peak window start
 };
 
 template <typename T, int NV, int NT>
@@ -368,20 +575,13 @@ __device__ __forceinline__ int mask_slot(const TelSmem& sm, int i) {
 
 // Phase 1 (fused): extraction of all pixels into LDS.  Returns this thread's
 // count of low-gain pixels.
-template <int PPL, int W, int CH, int NT>
+template <int EX, int PPL, int W, int CH, int NT>
 __device__ __forceinline__ int extract_phase(const DevCam& c, const uint16_t* __restrict__ ev, TelSmem& sm) {
-  const int N = c.n_pix, np = c.n_pix_pad, T = c.n_samp;
-  const bool dual = c.n_gain == 2;
+  const int N = c.n_pix, np = c.n_pix_pad;
   const __amdgpu_buffer_rsrc_t r = event_rsrc(ev, c.event_elems);
   int nlow = 0;
-  // Uniform pass loop: every lane streams (loads past the event read 0 from
-  // the bounds-checked buffer); only the stores are guarded by i < N.
-  const int npass = (N + NT * PPL - 1) / (NT * PPL);
-  for (int ps = 0; ps < npass; ++ps) {
-    const int pix0 = (ps * NT + (int)threadIdx.x) * PPL;
-    uint32_t key[PPL];
-    const uint32_t sw = extract_group<PPL, W, CH>(c, r, pix0, np, T, dual, key);
-    if (pix0 >= N) continue;
+  extract_event<EX, PPL, W, CH, NT>(c, r, sm.rows, &sm.start, [&](int pix0, const uint32_t (&key)[PPL], uint32_t sw) {
+    if (pix0 >= N) return;
     int32_t P[PPL], Tb[PPL], Tp[PPL];
     load_i32<PPL>(P, c.P256 + pix0);
     load_i32<PPL>(Tb, c.thr_bnd + pix0);
@@ -400,7 +600,7 @@ __device__ __forceinline__ int extract_phase(const DevCam& c, const uint16_t* __
         nlow += g;
       }
     }
-  }
+  });
   return nlow;
 }
 
@@ -625,10 +825,10 @@ __device__ __forceinline__ void hillas_phase(const DevCam& c, TelSmem& sm, int n
   if (threadIdx.x == 0) *out = r;
 }
 
-template <int PPL, int W, int CH, int NT>
+template <int EX, int PPL, int W, int CH, int NT>
 __device__ __forceinline__ void process_telescope(const DevCam& c, const uint16_t* __restrict__ ev, TelSmem& sm,
                                                   rta_hillas_rec* out) {
-  const int nlow = extract_phase<PPL, W, CH, NT>(c, ev, sm);
+  const int nlow = extract_phase<EX, PPL, W, CH, NT>(c, ev, sm);
   __syncthreads();
   mask_phase<NT>(c, sm);
   __syncthreads();
@@ -655,20 +855,18 @@ __device__ __forceinline__ void bad_record(rta_hillas_rec* out) {
 // ---------------------------------------------------------------------------
 
 // Unfused calibration: one workgroup per camera event, per-pixel results to HBM.
-template <int PPL, int W, int NT>
+template <int EX, int PPL, int W, int NT>
 __global__ __launch_bounds__(NT) void k_calibrate(DevCam c, const uint16_t* __restrict__ traces, int32_t* S,
                                                   int32_t* D, uint8_t* sstar, uint8_t* peak, uint8_t* gain,
                                                   float* q, float* t) {
+  __shared__ uint32_t rows[EX == kExGlobal ? NT / kWave * 256 : 1];
+  __shared__ int32_t start;
   const int64_t e = blockIdx.x;
   const int N = c.n_pix, np = c.n_pix_pad, T = c.n_samp;
   const uint16_t* ev = traces + e * c.event_elems;
   const size_t ob = (size_t)e * N;
   const __amdgpu_buffer_rsrc_t r = event_rsrc(ev, c.event_elems);
-  const int npass = (N + NT * PPL - 1) / (NT * PPL);
-  for (int ps = 0; ps < npass; ++ps) {
-    const int pix0 = (ps * NT + (int)threadIdx.x) * PPL;
-    uint32_t key[PPL];
-    const uint32_t sw = extract_group<PPL, W, 2 * W>(c, r, pix0, np, T, c.n_gain == 2, key);
+  extract_event<EX, PPL, W, 2 * W, NT>(c, r, rows, &start, [&](int pix0, const uint32_t (&key)[PPL], uint32_t sw) {
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
       const int i = pix0 + p;
@@ -688,7 +886,7 @@ __global__ __launch_bounds__(NT) void k_calibrate(DevCam c, const uint16_t* __re
       if (q) q[ob + i] = (float)d / (256.0f * c.a[g * np + i]);
       if (t) t[ob + i] = tv;
     }
-  }
+  });
 }
 
 template <int NT>
@@ -741,7 +939,7 @@ __global__ void k_queue_reset(unsigned long long* q) {
 
 // Per-telescope body of the fused kernel: descriptor checks, then
 // calibration -> cleaning -> Hillas with all intermediates in LDS.
-template <int PPL, int W, int CH, int NT>
+template <int EX, int PPL, int W, int CH, int NT>
 __device__ __forceinline__ void fused_telescope(const FusedArgs& a, long long tel, TelSmem& sm) {
   const int ty = uniform_i32(a.tel_type[tel]);
   const long long off = uniform_i64(a.tel_trace_off[tel]);
@@ -760,12 +958,12 @@ __device__ __forceinline__ void fused_telescope(const FusedArgs& a, long long te
     }
     return;
   }
-  process_telescope<PPL, W, CH, NT>(c, uniform_ptr(a.traces + off), sm, a.out + tel);
+  process_telescope<EX, PPL, W, CH, NT>(c, uniform_ptr(a.traces + off), sm, a.out + tel);
 }
 
 // Persistent form: a fixed grid of workgroups pulls telescopes from a global
 // counter until the batch is drained.
-template <int PPL, int W, int CH, int NT>
+template <int EX, int PPL, int W, int CH, int NT>
 __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
   __shared__ TelSmem sm;
   __shared__ long long s_tel;
@@ -775,7 +973,7 @@ __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
     const long long tel = uniform_i64(s_tel);
     __syncthreads();
     if (tel >= a.n_tel) return;
-    fused_telescope<PPL, W, CH, NT>(a, tel, sm);
+    fused_telescope<EX, PPL, W, CH, NT>(a, tel, sm);
     __syncthreads();
   }
 }
@@ -783,10 +981,10 @@ __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
 // Grid form: one workgroup per telescope, dispatched by the hardware's
 // workgroup scheduler (no loop-carried state, so no register pressure from
 // values hoisted across telescopes).
-template <int PPL, int W, int CH, int NT>
+template <int EX, int PPL, int W, int CH, int NT>
 __global__ __launch_bounds__(NT) void k_fused_grid(FusedArgs a) {
   __shared__ TelSmem sm;
-  fused_telescope<PPL, W, CH, NT>(a, (long long)blockIdx.x, sm);
+  fused_telescope<EX, PPL, W, CH, NT>(a, (long long)blockIdx.x, sm);
 }
 
 // One wavefront per array event: stereo direction from the telescope records
@@ -939,10 +1137,23 @@ constexpr int kUnfusedNT = 256;
 constexpr int kUnfusedPPL = 4;
 
 template <int W>
-hipError_t launch_calibrate_w(const DevCam& c, const uint16_t* tr, int64_t n, int32_t* S, int32_t* D, uint8_t* ss,
-                              uint8_t* pk, uint8_t* g, float* q, float* t, hipStream_t st) {
-  hipLaunchKernelGGL((k_calibrate<kUnfusedPPL, W, kUnfusedNT>), dim3((unsigned)n), dim3(kUnfusedNT), 0, st, c, tr,
-                     S, D, ss, pk, g, q, t);
+hipError_t launch_calibrate_w(const DevCam& c, int ex, const uint16_t* tr, int64_t n, int32_t* S, int32_t* D,
+                              uint8_t* ss, uint8_t* pk, uint8_t* g, float* q, float* t, hipStream_t st) {
+  switch (ex) {
+    case kExSliding:
+      hipLaunchKernelGGL((k_calibrate<kExSliding, kUnfusedPPL, W, kUnfusedNT>), dim3((unsigned)n), dim3(kUnfusedNT),
+                         0, st, c, tr, S, D, ss, pk, g, q, t);
+      break;
+    case kExFixed:
+      hipLaunchKernelGGL((k_calibrate<kExFixed, kUnfusedPPL, W, kUnfusedNT>), dim3((unsigned)n), dim3(kUnfusedNT), 0,
+                         st, c, tr, S, D, ss, pk, g, q, t);
+      break;
+    case kExGlobal:
+      hipLaunchKernelGGL((k_calibrate<kExGlobal, kUnfusedPPL, W, kUnfusedNT>), dim3((unsigned)n), dim3(kUnfusedNT),
+                         0, st, c, tr, S, D, ss, pk, g, q, t);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -953,13 +1164,22 @@ hipError_t launch_hillas_w(const DevCam& c, const int32_t* D, const uint8_t* g, 
   return hipGetLastError();
 }
 
-// grid == 0: one workgroup per telescope; otherwise the persistent form.
+// grid == 0: one workgroup per telescope; otherwise the persistent form
+// (sliding window only: the other extractors always use the grid form).
 template <int PPL, int W, int CH, int NT>
 hipError_t launch_fused_t(const FusedArgs& a, int grid, hipStream_t st) {
-  if (grid == 0)
-    hipLaunchKernelGGL((k_fused_grid<PPL, W, CH, NT>), dim3((unsigned)a.n_tel), dim3(NT), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_fused<PPL, W, CH, NT>), dim3(grid), dim3(NT), 0, st, a);
+  const dim3 g1((unsigned)a.n_tel);
+  switch (a.extractor) {
+    case kExSliding:
+      if (grid == 0)
+        hipLaunchKernelGGL((k_fused_grid<kExSliding, PPL, W, CH, NT>), g1, dim3(NT), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_fused<kExSliding, PPL, W, CH, NT>), dim3(grid), dim3(NT), 0, st, a);
+      break;
+    case kExFixed: hipLaunchKernelGGL((k_fused_grid<kExFixed, PPL, W, CH, NT>), g1, dim3(NT), 0, st, a); break;
+    case kExGlobal: hipLaunchKernelGGL((k_fused_grid<kExGlobal, PPL, W, CH, NT>), g1, dim3(NT), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -987,6 +1207,8 @@ hipError_t launch_fused_w(const FusedArgs& a, const rta_schedule& s, int grid, h
 
 bool window_supported(int w) { return w == 4; }
 
+bool extractor_supported(int ex) { return ex == kExSliding || ex == kExFixed || ex == kExGlobal; }
+
 bool schedule_supported(const rta_schedule& s) {
   const bool ppl = s.pix_per_lane == 2 || s.pix_per_lane == 4 || s.pix_per_lane == 8;
   const bool wv = s.waves_per_wg == 4 || s.waves_per_wg == 8;
@@ -1007,10 +1229,11 @@ int list_schedules(rta_schedule* out, int cap) {
   return n;
 }
 
-hipError_t launch_calibrate(const DevCam& c, const uint16_t* traces, int64_t n_evt, int32_t* S, int32_t* D,
-                            uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q, float* t, hipStream_t st) {
+hipError_t launch_calibrate(const DevCam& c, int extractor, const uint16_t* traces, int64_t n_evt, int32_t* S,
+                            int32_t* D, uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q, float* t,
+                            hipStream_t st) {
   switch (c.window) {
-    case 4: return launch_calibrate_w<4>(c, traces, n_evt, S, D, sstar, peak, gain, q, t, st);
+    case 4: return launch_calibrate_w<4>(c, extractor, traces, n_evt, S, D, sstar, peak, gain, q, t, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1038,7 +1261,7 @@ hipError_t launch_fused(const FusedArgs& a, const rta_schedule& s, int n_cu, hip
   long long grid = (long long)n_cu * s.wg_per_cu;
   if (grid > a.n_tel) grid = a.n_tel;
   if (grid < 1) grid = 1;
-  if (s.wg_per_cu == 0) grid = 0;
+  if (s.wg_per_cu == 0 || a.extractor != kExSliding) grid = 0;
   switch (a.window) {
     case 4: return launch_fused_w<4>(a, s, (int)grid, st);
     default: return hipErrorInvalidValue;

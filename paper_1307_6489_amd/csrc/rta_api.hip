@@ -72,6 +72,8 @@ rta_status launch_batch(rta_pipeline* pipe, const rta_batch* b, rta_hillas_rec* 
   for (size_t i = 0; i < pipe->cams.size(); ++i) fa.cams[i] = pipe->cams[i]->dev;
   fa.n_types = (int32_t)pipe->cams.size();
   fa.window = pipe->window;
+  fa.extractor = pipe->params.extractor;
+  fa.pad_ = 0;
   fa.traces = b->traces;
   fa.traces_len = b->traces_len;
   fa.tel_type = b->tel_type;
@@ -158,6 +160,8 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
   if (!std::isfinite(d->t_pic) || !std::isfinite(d->t_bnd) || d->t_bnd > d->t_pic)
     return fail(RTA_E_INVALID_ARG, "cleaning levels must be finite with t_bnd <= t_pic");
   if (!std::isfinite(d->focal_m) || !(d->focal_m > 0.f)) return fail(RTA_E_INVALID_ARG, "focal length must be > 0");
+  if (d->fixed_start < 0 || d->fixed_start > T - w)
+    return fail(RTA_E_SHAPE, "fixed_start must be in [0, n_samp - window]");
   const int Np = (N + 7) & ~7;
   std::vector<int32_t> P(G * Np, 0), Tp(G * Np, 0x7fffffff), Tb(G * Np, 0x7fffffff);
   std::vector<float> A(G * Np, 1.f), X(Np, 0.f), Y(Np, 0.f);
@@ -225,7 +229,7 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
   c.hg_switch = d->hg_switch_adc;
   c.event_elems = (int64_t)G * T * Np;
   c.focal = d->focal_m;
-  c.pad_ = 0;
+  c.fixed_start = d->fixed_start;
   c.P256 = reinterpret_cast<const int32_t*>(base + oP);
   c.thr_pic = reinterpret_cast<const int32_t*>(base + oTp);
   c.thr_bnd = reinterpret_cast<const int32_t*>(base + oTb);
@@ -234,7 +238,7 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
   c.y = reinterpret_cast<const float*>(base + oY);
   c.nbr = reinterpret_cast<const int16_t*>(base + oN);
   c.border = base + oB;
-  cam->info = rta_camera_info{N, Np, T, G, w, 0, c.event_elems};
+  cam->info = rta_camera_info{N, Np, T, G, w, d->fixed_start, c.event_elems};
   *out = cam;
   return RTA_OK;
 }
@@ -254,12 +258,20 @@ rta_status rta_camera_get_info(const rta_camera* cam, rta_camera_info* info) {
 
 rta_status rta_calibrate(const rta_camera* cam, const uint16_t* traces, int64_t n_evt, int32_t* S, int32_t* D,
                          uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q, float* t, rta_stream stream) {
+  return rta_calibrate_ex(cam, RTA_EXTRACT_SLIDING, traces, n_evt, S, D, sstar, peak, gain, q, t, stream);
+}
+
+rta_status rta_calibrate_ex(const rta_camera* cam, int32_t extractor, const uint16_t* traces, int64_t n_evt,
+                            int32_t* S, int32_t* D, uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q,
+                            float* t, rta_stream stream) {
   if (!cam) return fail(RTA_E_INVALID_ARG, "null camera");
+  if (!rta::extractor_supported(extractor)) return fail(RTA_E_INVALID_ARG, "unknown extractor");
   if (n_evt < 0) return fail(RTA_E_INVALID_ARG, "negative event count");
   if (n_evt > 0x7fffffffLL) return fail(RTA_E_SHAPE, "too many events for one launch");
   if (n_evt == 0) return RTA_OK;
   if (!traces || !aligned16(traces)) return fail(RTA_E_INVALID_ARG, "traces must be non-null and 16-byte aligned");
-  RTA_HIP(rta::launch_calibrate(cam->dev, traces, n_evt, S, D, sstar, peak, gain, q, t, (hipStream_t)stream));
+  RTA_HIP(rta::launch_calibrate(cam->dev, extractor, traces, n_evt, S, D, sstar, peak, gain, q, t,
+                                (hipStream_t)stream));
   return RTA_OK;
 }
 
@@ -295,6 +307,7 @@ rta_status rta_pipeline_create(rta_camera* const* cams, int32_t n_types, const r
     if (!cams[i]) return fail(RTA_E_INVALID_ARG, "null camera handle");
   for (int i = 1; i < n_types; ++i)
     if (cams[i]->dev.window != cams[0]->dev.window) return fail(RTA_E_SHAPE, "all camera types need one window");
+  if (!rta::extractor_supported(params->extractor)) return fail(RTA_E_INVALID_ARG, "unknown extractor");
   if (params->do_stereo && (!(params->max_width_ratio > 0.f) || !(params->max_cond > 1.f)))
     return fail(RTA_E_INVALID_ARG, "stereo cuts must be positive");
   rta_pipeline* p = new (std::nothrow) rta_pipeline();

@@ -20,7 +20,7 @@ struct DevCam {
   int32_t window, hg_switch;
   int64_t event_elems;
   float focal;
-  int32_t pad_;
+  int32_t fixed_start;     // first sample of the fixed extraction window
   const int32_t* P256;     // [G][Npad] Q8 pedestal per sample
   const int32_t* thr_pic;  // [G][Npad] Q8 picture threshold (on D)
   const int32_t* thr_bnd;  // [G][Npad] Q8 boundary threshold (on D)
@@ -57,6 +57,8 @@ struct FusedArgs {
   DevCam cams[RTA_MAX_TYPES];
   int32_t n_types;
   int32_t window;
+  int32_t extractor;       // RTA_EXTRACT_*
+  int32_t pad_;
   const uint16_t* traces;
   int64_t traces_len;
   const int32_t* tel_type;
@@ -93,8 +95,9 @@ hipError_t launch_mlp_adam(const MlpDev& w, bool update, float lr, float b1, flo
                            hipStream_t st);
 
 // Kernel launchers (reco.hip).  Each returns the launch status.
-hipError_t launch_calibrate(const DevCam& c, const uint16_t* traces, int64_t n_evt, int32_t* S, int32_t* D,
-                            uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q, float* t, hipStream_t st);
+hipError_t launch_calibrate(const DevCam& c, int extractor, const uint16_t* traces, int64_t n_evt, int32_t* S,
+                            int32_t* D, uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q, float* t,
+                            hipStream_t st);
 hipError_t launch_clean(const DevCam& c, const int32_t* D, const uint8_t* gain, int64_t n_evt, uint8_t* mask,
                         hipStream_t st);
 hipError_t launch_hillas(const DevCam& c, const int32_t* D, const uint8_t* gain, const float* t,
@@ -107,6 +110,7 @@ hipError_t launch_classify(const MlpDev& w, bool have_mlp, const rta_boxcut_desc
                            int64_t n, float* out, hipStream_t st);
 
 bool window_supported(int w);
+bool extractor_supported(int ex);
 bool schedule_supported(const rta_schedule& s);
 int list_schedules(rta_schedule* out, int cap);
 
