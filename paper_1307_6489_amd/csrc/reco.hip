@@ -359,9 +359,17 @@ __device__ __forceinline__ uint32_t fixed_group(const DevCam& c, __amdgpu_buffer
   return sw;
 }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-  for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+// Sum of v over the wavefront, valid in lane 63, with DPP lane moves only
+// (no LDS traffic): pairs and quads by quad permutes, eights and sixteens by
+// the half-row and row mirrors, then rows by the row-15 and row-31
+// broadcasts (rows outside the row mask add 0).
+__device__ __forceinline__ uint32_t wave_sum_u32_last(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
   return v;
 }
 
@@ -381,7 +389,7 @@ __device__ __forceinline__ uint32_t global_rows_group(const DevCam& c, __amdgpu_
     msk[h] = (2 * h + 1 < nv) ? 0xffffffffu : (2 * h < nv ? 0x0000ffffu : 0u);
     rmax[h] = 0;
   }
-  const bool writer = (threadIdx.x & (kWave - 1)) == 0;
+  const bool writer = (threadIdx.x & (kWave - 1)) == kWave - 1;
   uint32_t A[CH][ND];
   for (int k0 = 0; k0 < T; k0 += CH) {
     load_chunk<PPL, CH>(A, r, voff, 0u, stride, k0);
@@ -395,7 +403,7 @@ __device__ __forceinline__ uint32_t global_rows_group(const DevCam& c, __amdgpu_
         v += lo16(x) + hi16(x);
         rmax[h] = pkmax16(rmax[h], x);
       }
-      v = wave_sum_u32(v);
+      v = wave_sum_u32_last(v);
       if (writer) rows[k0 + j] = first ? v : rows[k0 + j] + v;
     }
   }
