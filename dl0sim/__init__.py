@@ -117,6 +117,10 @@ def _declare(L):
     L.dl0sim_philox4x32_10.restype = None
     L.dl0sim_shower_size.argtypes = []
     L.dl0sim_shower_size.restype = ctypes.c_int
+    L.dl0sim_crc16.argtypes = [vp, i64]
+    L.dl0sim_crc16.restype = ctypes.c_uint16
+    L.dl0sim_serialize_packets.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
+    L.dl0sim_serialize_packets.restype = None
 
 
 def philox4x32_10(ctr, key):

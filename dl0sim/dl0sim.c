@@ -553,3 +553,74 @@ void dl0sim_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t
 }
 
 int dl0sim_shower_size(void) { return (int)sizeof(dl0sim_shower); }
+
+/* ------------------------------------------------------------------ */
+/* DL0 telemetry packets                                                */
+/*                                                                      */
+/* The project's packet format for camera events on the byte stream    */
+/* between the event builder and the analysis (in the style of space   */
+/* telemetry source packets; every multi-byte field big-endian):       */
+/*   0  u16  packet id: version 0 (3 b) | type 0 (1 b) | secondary     */
+/*           header 1 (1 b) | APID = telescope id (11 b)                */
+/*   2  u16  sequence control: flags 0b11 (unsegmented) | count (14 b) */
+/*   4  u32  packet data length = total length - 9                     */
+/*   8  u8   0x10   9 u8 service 210   10 u8 subtype 1                 */
+/*  11  u8   camera type   12 u32 coarse time   16 u16 fine time       */
+/*  18  u16  n_pix   20 u16 n_samp   22 u8 n_gain   23 u8 spare (0)    */
+/*  24  u64  event number                                               */
+/*  32  u16  samples [G][T][N] (no padding)                            */
+/*  end u16  CRC-16 (poly 0x1021, init 0xFFFF) of every byte before it */
+/* ------------------------------------------------------------------ */
+static uint16_t crc_table_gen[256];
+static int crc_table_ready = 0;
+
+static void crc_table_init(void) {
+  for (int i = 0; i < 256; ++i) {
+    uint16_t r = (uint16_t)(i << 8);
+    for (int k = 0; k < 8; ++k) r = (uint16_t)((r & 0x8000) ? (r << 1) ^ 0x1021 : (r << 1));
+    crc_table_gen[i] = r;
+  }
+  crc_table_ready = 1;
+}
+
+uint16_t dl0sim_crc16(const uint8_t* p, int64_t n) {
+  if (!crc_table_ready) crc_table_init();
+  uint16_t c = 0xFFFF;
+  for (int64_t i = 0; i < n; ++i) c = (uint16_t)((c << 8) ^ crc_table_gen[((c >> 8) ^ p[i]) & 0xFF]);
+  return c;
+}
+
+static void put16(uint8_t* p, uint32_t v) { p[0] = (uint8_t)(v >> 8); p[1] = (uint8_t)v; }
+static void put32(uint8_t* p, uint32_t v) { put16(p, v >> 16); put16(p + 2, v); }
+
+/* One packet per camera event.  meta [n][8] int64: camera type, n_pix,
+ * n_samp, n_gain, Npad, element offset of the event in blob, APID,
+ * sequence count; evno [n], coarse [n] (u32), fine [n] (u16); out_off [n]
+ * byte offset of each packet in out (the caller lays them out). */
+void dl0sim_serialize_packets(int64_t n, const int64_t* meta, const uint64_t* evno, const uint32_t* coarse,
+                              const uint16_t* fine, const uint16_t* blob, const int64_t* out_off, uint8_t* out) {
+  if (!crc_table_ready) crc_table_init();
+  for (int64_t e = 0; e < n; ++e) {
+    const int64_t* m = meta + 8 * e;
+    const int ty = (int)m[0], N = (int)m[1], T = (int)m[2], G = (int)m[3], Np = (int)m[4];
+    const uint16_t* ev = blob + m[5];
+    uint8_t* p = out + out_off[e];
+    const int64_t body = 2LL * G * T * N, total = 32 + body + 2;
+    put16(p, (1u << 11) | ((uint32_t)m[6] & 0x7FFu));
+    put16(p + 2, (3u << 14) | ((uint32_t)m[7] & 0x3FFFu));
+    put32(p + 4, (uint32_t)(total - 9));
+    p[8] = 0x10; p[9] = 210; p[10] = 1; p[11] = (uint8_t)ty;
+    put32(p + 12, coarse[e]);
+    put16(p + 16, fine[e]);
+    put16(p + 18, (uint32_t)N);
+    put16(p + 20, (uint32_t)T);
+    p[22] = (uint8_t)G; p[23] = 0;
+    put32(p + 24, (uint32_t)(evno[e] >> 32));
+    put32(p + 28, (uint32_t)evno[e]);
+    uint8_t* q = p + 32;
+    for (int g = 0; g < G; ++g)
+      for (int k = 0; k < T; ++k)
+        for (int i = 0; i < N; ++i, q += 2) put16(q, ev[((int64_t)g * T + k) * Np + i]);
+    put16(p + 32 + body, dl0sim_crc16(p, 32 + body));
+  }
+}

@@ -88,6 +88,8 @@ def lib():
         L.oracle_reconstruct_event.argtypes = [vp, vp, vp, vp, vp]
         L.oracle_stereo.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.oracle_reconstruct_batch.argtypes = [vp, i64, vp, vp, vp, vp, i32]
+        L.oracle_crc16.argtypes = [vp, i64]
+        L.oracle_crc16.restype = ctypes.c_uint16
         for f in ("oracle_sizeof_cam", "oracle_sizeof_pix", "oracle_sizeof_hillas"):
             getattr(L, f).restype = ctypes.c_int
         assert L.oracle_sizeof_cam() == ctypes.sizeof(OracleCam)

@@ -421,3 +421,17 @@ void oracle_reconstruct_batch(const oracle_cam* cams, int64_t n_evt, const int32
 int oracle_sizeof_cam(void) { return (int)sizeof(oracle_cam); }
 int oracle_sizeof_pix(void) { return (int)sizeof(oracle_pix); }
 int oracle_sizeof_hillas(void) { return (int)sizeof(oracle_hillas); }
+
+/* ------------------------------------------------------------------ */
+/* CRC-16 of the DL0 telemetry packets: polynomial x^16+x^12+x^5+1,    */
+/* initial register 0xFFFF, bits most-significant first, no final xor, */
+/* computed bit by bit from the definition (no table).                 */
+/* ------------------------------------------------------------------ */
+uint16_t oracle_crc16(const uint8_t* p, int64_t n) {
+  uint32_t c = 0xFFFF;
+  for (int64_t i = 0; i < n; ++i) {
+    c ^= (uint32_t)p[i] << 8;
+    for (int b = 0; b < 8; ++b) c = (c & 0x8000) ? ((c << 1) ^ 0x1021) & 0xFFFF : (c << 1) & 0xFFFF;
+  }
+  return (uint16_t)c;
+}
