@@ -109,6 +109,7 @@ typedef enum rta_status {
 #define RTA_STATUS_BAD_TYPE 0x1u
 #define RTA_STATUS_BAD_OFFSET 0x2u
 #define RTA_STATUS_BAD_EVENT 0x4u
+#define RTA_STATUS_BAD_PACKET 0x8u
 
 typedef void* rta_stream; /* hipStream_t */
 
@@ -262,6 +263,66 @@ rta_status rta_graph_capture(rta_pipeline* pipe, const rta_batch* batch, rta_hil
                              rta_event_rec* evt_out, rta_graph** out);
 rta_status rta_graph_launch(rta_graph* g, rta_stream stream);
 rta_status rta_graph_destroy(rta_graph* g);
+
+/* ------------------------------------------------------------------------
+ * DL0 telemetry packets: the byte stream of camera events between the event
+ * builder and the analysis, formatted in the manner of space telemetry
+ * source packets (paper, Section 5).  One packet per camera event, every
+ * multi-byte field big-endian:
+ *    0  u16  packet id: version 0 (3 bits) | type 0 (1 bit) | secondary
+ *            header flag 1 (1 bit) | APID = telescope id (11 bits)
+ *    2  u16  sequence control: flags 0b11 (2 bits) | sequence count (14 bits)
+ *    4  u32  packet data length = total packet length - 9
+ *    8  u8   0x10    9  u8 service 210    10  u8 subtype 1
+ *   11  u8   camera type (index into the pipeline's camera list)
+ *   12  u32  coarse time    16  u16 fine time
+ *   18  u16  n_pix    20  u16 n_samp    22  u8 n_gain    23  u8 spare (0)
+ *   24  u64  event number
+ *   32  u16  samples [G][T][N] (no padding)
+ *  end  u16  CRC-16 of every byte before it: polynomial x^16+x^12+x^5+1,
+ *            register 0xFFFF, most significant bit first, no final xor.
+ * ------------------------------------------------------------------------ */
+#define RTA_PKT_HEADER_BAD 0x1u  /* fixed fields, flags or length inconsistent */
+#define RTA_PKT_TYPE_BAD 0x2u    /* camera type unknown / dimensions differ / no pool slot */
+#define RTA_PKT_CRC_BAD 0x4u     /* CRC mismatch */
+
+/* Per-packet record written by rta_decode_packets, 32 bytes. */
+typedef struct rta_packet_rec {
+  uint64_t event_number;
+  uint32_t coarse_time;
+  uint16_t fine_time, apid, seq_count, cam_type;
+  uint32_t flags;                     /* RTA_PKT_* */
+  uint16_t crc_stored, crc_computed;  /* valid when the header and type were good */
+  uint32_t pad_;
+} rta_packet_rec;
+
+/* Framing on the host (all pointers HOST memory; nothing is launched):
+ * walks the packet headers of bytes[0, n_bytes) from offset 0.  For each
+ * whole packet (at most cap): pkt_off = its byte offset; tel_type = its
+ * camera type if that is < n_types and the header's n_pix / n_samp / n_gain
+ * equal types[t]'s, else -1; tel_trace_off = the element offset of its slot
+ * in the decoded pool (slots of G*T*Npad elements in packet order; 0 and no
+ * slot for type -1).  Outputs the packet count, the pool size in elements
+ * and the bytes consumed (the start of a trailing partial packet, which
+ * belongs to the next chunk).  RTA_E_SHAPE if a data length implies a
+ * packet shorter than 34 bytes (framing lost; *consumed = its offset). */
+rta_status rta_frame_packets(const rta_camera_info* types, int32_t n_types, const uint8_t* bytes, int64_t n_bytes,
+                             int64_t cap, int64_t* pkt_off, int32_t* tel_type, int64_t* tel_trace_off,
+                             int64_t* n_pkt, int64_t* pool_elems, int64_t* consumed);
+
+/* Decode on the device (all pointers DEVICE memory): one workgroup per
+ * packet checks the header, the camera type against tel_type[p] and the
+ * pipeline's camera dimensions, and the CRC (computed in parallel, each
+ * lane folding its 16-byte column pieces by the linearity of the CRC over
+ * GF(2)), and writes the samples little-endian into pool[tel_trace_off[p]
+ * ...] as [G][T][Npad] with zero pad columns.  A packet failing any check
+ * gets tel_type[p] = -1 (in place: the fused batch then flags it as a bad
+ * descriptor), its record's flags and RTA_STATUS_BAD_PACKET in the status
+ * word; a CRC failure is known only after its slot was written.
+ * bytes: 16-byte aligned.  rec: [n_pkt], NULLABLE. */
+rta_status rta_decode_packets(rta_pipeline* pipe, const uint8_t* bytes, int64_t n_bytes, const int64_t* pkt_off,
+                              int32_t* tel_type, const int64_t* tel_trace_off, int64_t n_pkt, uint16_t* pool,
+                              int64_t pool_elems, rta_packet_rec* rec, rta_stream stream);
 
 /* ------------------------------------------------------------------------
  * Gamma/hadron + energy network (the separation and energy steps of the

@@ -32,6 +32,10 @@ EVT_NO_MLP = 0x2
 STATUS_BAD_TYPE = 0x1
 STATUS_BAD_OFFSET = 0x2
 STATUS_BAD_EVENT = 0x4
+STATUS_BAD_PACKET = 0x8
+PKT_HEADER_BAD = 0x1
+PKT_TYPE_BAD = 0x2
+PKT_CRC_BAD = 0x4
 MAX_PIX = 2048
 MAX_SAMP = 255
 MAX_TYPES = 8
@@ -83,6 +87,10 @@ HILLAS_DTYPE = np.dtype([(f, "<f4") for f in HILLAS_FIELDS]
 EVENT_DTYPE = np.dtype([("dir_x", "<f4"), ("dir_y", "<f4"), ("cond", "<f4"), ("gammaness", "<f4"),
                         ("log10_energy", "<f4"), ("n_tel", "<i4"), ("n_used", "<i4"), ("flags", "<u4")])
 
+PACKET_DTYPE = np.dtype([("event_number", "<u8"), ("coarse_time", "<u4"), ("fine_time", "<u2"), ("apid", "<u2"),
+                         ("seq_count", "<u2"), ("cam_type", "<u2"), ("flags", "<u4"), ("crc_stored", "<u2"),
+                         ("crc_computed", "<u2"), ("pad_", "<u4")])
+
 # C symbols declared in include/rta.h: name -> (argtypes, restype)
 _vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
 SYMBOLS = {
@@ -108,6 +116,8 @@ SYMBOLS = {
     "rta_graph_capture": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "rta_graph_launch": ([_vp, _vp], ctypes.c_int),
     "rta_graph_destroy": ([_vp], ctypes.c_int),
+    "rta_frame_packets": ([_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "rta_decode_packets": ([_vp, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_mlp_create": ([_vp, _vp], ctypes.c_int),
     "rta_mlp_destroy": ([_vp], ctypes.c_int),
     "rta_mlp_set_params": ([_vp, _vp, _vp, _vp], ctypes.c_int),
@@ -223,6 +233,7 @@ class Camera:
         self.n_pix, self.n_pix_pad, self.n_samp = info.n_pix, info.n_pix_pad, info.n_samp
         self.n_gain, self.window, self.event_elems = info.n_gain, info.window, info.event_elems
         self.fixed_start = info.fixed_start
+        self.n_pix_pad = info.n_pix_pad
         self.focal_m = focal_m
 
     @classmethod
@@ -377,6 +388,51 @@ class Pipeline:
 
     def capture(self, batch, tel_out, evt_out=None):
         return Graph(self, batch, tel_out, evt_out)
+
+
+def frame_packets(cams, data, cap=None):
+    """Host framing of a DL0 packet stream (``data``: host uint8 array) for
+    the camera types ``cams`` (list of Camera, index = camera type).
+    Returns (pkt_off int64, tel_type int32, tel_trace_off int64, pool_elems,
+    consumed bytes) as numpy arrays / ints."""
+    data = np.ascontiguousarray(data, np.uint8).reshape(-1)
+    infos = (CameraInfo * max(len(cams), 1))()
+    for i, c in enumerate(cams):
+        infos[i] = CameraInfo(c.n_pix, c.n_pix_pad, c.n_samp, c.n_gain, c.window, c.fixed_start, c.event_elems)
+    cap = data.size // 34 + 1 if cap is None else int(cap)
+    off = np.empty(cap, np.int64)
+    ty = np.empty(cap, np.int32)
+    toff = np.empty(cap, np.int64)
+    n, pool, used = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().rta_frame_packets(infos, len(cams), data.ctypes.data_as(ctypes.c_void_p), data.size, cap,
+                                   off.ctypes.data_as(ctypes.c_void_p), ty.ctypes.data_as(ctypes.c_void_p),
+                                   toff.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n), ctypes.byref(pool),
+                                   ctypes.byref(used)))
+    k = n.value
+    return off[:k].copy(), ty[:k].copy(), toff[:k].copy(), pool.value, used.value
+
+
+def decode_packets(pipe, data, pkt_off, tel_type, tel_trace_off, pool_elems, pool=None, stream=None, want_rec=True):
+    """Device decode of framed packets: ``data`` uint8 device tensor (16-byte
+    aligned), ``pkt_off`` / ``tel_trace_off`` int64 and ``tel_type`` int32
+    device tensors (tel_type is rewritten in place: -1 for rejected packets).
+    Returns (pool uint16 tensor, packet records [n][8] float32-viewed tensor
+    or None)."""
+    import torch
+    _require(data, torch.uint8, name="data")
+    _require(pkt_off, torch.int64, name="pkt_off")
+    _require(tel_type, torch.int32, name="tel_type")
+    _require(tel_trace_off, torch.int64, name="tel_trace_off")
+    n = pkt_off.numel()
+    if tel_type.numel() != n or tel_trace_off.numel() != n:
+        raise ValueError("packet arrays differ in length")
+    if pool is None:
+        pool = torch.empty(max(int(pool_elems), 8), dtype=torch.uint16, device=data.device)
+    rec = torch.empty((n, 8), dtype=torch.float32, device=data.device) if want_rec else None
+    _check(lib().rta_decode_packets(pipe.handle, _ptr(data), data.numel(), _ptr(pkt_off), _ptr(tel_type),
+                                    _ptr(tel_trace_off), n, _ptr(pool), int(pool_elems), _ptr(rec),
+                                    _stream(stream)))
+    return pool, rec
 
 
 class Graph:

@@ -125,6 +125,7 @@ __device__ __forceinline__ DevCam uniform_cam(const DevCam& c) {
   u.y = uniform_ptr(c.y);
   u.nbr = uniform_ptr(c.nbr);
   u.border = uniform_ptr(c.border);
+  u.crc_tab = uniform_ptr(c.crc_tab);
   return u;
 }
 

@@ -1,4 +1,5 @@
 // C ABI of librta: argument validation, camera tables, pipelines, graphs.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -62,6 +63,45 @@ rta_status fail(rta_status s, const std::string& msg) {
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 size_t round256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Product of two residues modulo the packet CRC polynomial x^16+x^12+x^5+1
+// (polynomials over GF(2), bit i = coefficient of x^i).
+uint32_t gf_mul(uint32_t a, uint32_t b) {
+  uint32_t r = 0;
+  for (int i = 15; i >= 0; --i) {
+    r <<= 1;
+    if (r & 0x10000u) r ^= 0x11021u;
+    if ((b >> i) & 1u) r ^= a;
+  }
+  return r;
+}
+
+// x^(8n) modulo the CRC polynomial.
+uint32_t gf_pow8(uint64_t n) {
+  uint32_t res = 1, base = 0x100;
+  while (n) {
+    if (n & 1) res = gf_mul(res, base);
+    base = gf_mul(base, base);
+    n >>= 1;
+  }
+  return res;
+}
+
+// Constants of the parallel packet CRC for one camera type (layout in DevCam).
+void crc_tables(int N, int T, int G, uint16_t* t) {
+  const uint64_t row = 2ull * (uint64_t)N, body = row * (uint64_t)T * (uint64_t)G;
+  const uint32_t K = gf_pow8(row);
+  for (uint32_t i = 0; i < 256; ++i) {
+    t[i] = (uint16_t)gf_mul(i, K);
+    t[256 + i] = (uint16_t)gf_mul(i << 8, K);
+  }
+  for (int l = 0; l < rta::kDecodeNT; ++l) {
+    const uint64_t lo = 16ull * (uint64_t)l;
+    t[512 + l] = (uint16_t)(lo < row ? gf_pow8(row - std::min<uint64_t>(lo + 16, row)) : 1u);
+  }
+  t[768] = (uint16_t)gf_pow8(body);
+  t[769] = (uint16_t)gf_mul(0xFFFFu, gf_pow8(32 + body));
+}
 
 void fill_event_args(const rta_pipeline* pipe, rta::EventArgs& ea);
 
@@ -167,6 +207,8 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
   std::vector<float> A(G * Np, 1.f), X(Np, 0.f), Y(Np, 0.f);
   std::vector<int16_t> nb(Np * rta::kNbrCols, -1);
   std::vector<uint8_t> border(Np, 0);
+  std::vector<uint16_t> crc(rta::kCrcTabLen, 0);
+  crc_tables(N, T, G, crc.data());
   for (int g = 0; g < G; ++g)
     for (int i = 0; i < N; ++i) {
       const float ped = d->ped[g * N + i], a = d->adc_per_pe[g * N + i];
@@ -198,7 +240,8 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
   const size_t oP = 0, oTp = oP + round256(P.size() * 4), oTb = oTp + round256(Tp.size() * 4);
   const size_t oA = oTb + round256(Tb.size() * 4), oX = oA + round256(A.size() * 4);
   const size_t oY = oX + round256(X.size() * 4), oN = oY + round256(Y.size() * 4);
-  const size_t oB = oN + round256(nb.size() * 2), total = oB + round256(border.size());
+  const size_t oB = oN + round256(nb.size() * 2), oC = oB + round256(border.size());
+  const size_t total = oC + round256(crc.size() * 2);
   std::vector<uint8_t> host(total, 0);
   std::memcpy(host.data() + oP, P.data(), P.size() * 4);
   std::memcpy(host.data() + oTp, Tp.data(), Tp.size() * 4);
@@ -208,6 +251,7 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
   std::memcpy(host.data() + oY, Y.data(), Y.size() * 4);
   std::memcpy(host.data() + oN, nb.data(), nb.size() * 2);
   std::memcpy(host.data() + oB, border.data(), border.size());
+  std::memcpy(host.data() + oC, crc.data(), crc.size() * 2);
   rta_camera* cam = new (std::nothrow) rta_camera();
   if (!cam) return fail(RTA_E_NOMEM, "host allocation failed");
   if (hipGetDevice(&cam->device) != hipSuccess || hipMalloc(&cam->dmem, total) != hipSuccess) {
@@ -238,6 +282,7 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
   c.y = reinterpret_cast<const float*>(base + oY);
   c.nbr = reinterpret_cast<const int16_t*>(base + oN);
   c.border = base + oB;
+  c.crc_tab = reinterpret_cast<const uint16_t*>(base + oC);
   cam->info = rta_camera_info{N, Np, T, G, w, d->fixed_start, c.event_elems};
   *out = cam;
   return RTA_OK;
@@ -398,6 +443,73 @@ rta_status rta_batch_status(rta_pipeline* p, uint32_t* status) {
   RTA_HIP(hipMemcpy(status, p->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost));
   RTA_HIP(hipMemset(p->d_status, 0, sizeof(uint32_t)));
   RTA_HIP(hipDeviceSynchronize());
+  return RTA_OK;
+}
+
+rta_status rta_frame_packets(const rta_camera_info* types, int32_t n_types, const uint8_t* bytes, int64_t n_bytes,
+                             int64_t cap, int64_t* pkt_off, int32_t* tel_type, int64_t* tel_trace_off,
+                             int64_t* n_pkt, int64_t* pool_elems, int64_t* consumed) {
+  if (!n_pkt || !pool_elems || !consumed) return fail(RTA_E_INVALID_ARG, "null count output");
+  *n_pkt = *pool_elems = *consumed = 0;
+  if (n_types < 0 || n_types > RTA_MAX_TYPES || (n_types > 0 && !types)) return fail(RTA_E_INVALID_ARG, "bad types");
+  if (n_bytes < 0 || cap < 0 || (n_bytes > 0 && !bytes) || (cap > 0 && (!pkt_off || !tel_type || !tel_trace_off)))
+    return fail(RTA_E_INVALID_ARG, "null or negative argument");
+  auto u16 = [&](int64_t o) { return (uint32_t)bytes[o] << 8 | bytes[o + 1]; };
+  int64_t pos = 0, n = 0, pool = 0;
+  while (pos + 8 <= n_bytes && n < cap) {
+    const int64_t total = (int64_t)((u16(pos + 4) << 16) | u16(pos + 6)) + 9;
+    if (total < 34) {
+      *n_pkt = n;
+      *pool_elems = pool;
+      *consumed = pos;
+      return fail(RTA_E_SHAPE, "packet framing lost (data length below the smallest packet)");
+    }
+    if (pos + total > n_bytes) break;
+    const int ty = bytes[pos + 11];
+    const int N = (int)u16(pos + 18), T = (int)u16(pos + 20), G = bytes[pos + 22];
+    pkt_off[n] = pos;
+    if (ty < n_types && types[ty].n_pix == N && types[ty].n_samp == T && types[ty].n_gain == G) {
+      tel_type[n] = ty;
+      tel_trace_off[n] = pool;
+      pool += types[ty].event_elems;
+    } else {
+      tel_type[n] = -1;
+      tel_trace_off[n] = 0;
+    }
+    ++n;
+    pos += total;
+  }
+  *n_pkt = n;
+  *pool_elems = pool;
+  *consumed = pos;
+  return RTA_OK;
+}
+
+rta_status rta_decode_packets(rta_pipeline* pipe, const uint8_t* bytes, int64_t n_bytes, const int64_t* pkt_off,
+                              int32_t* tel_type, const int64_t* tel_trace_off, int64_t n_pkt, uint16_t* pool,
+                              int64_t pool_elems, rta_packet_rec* rec, rta_stream stream) {
+  if (!pipe) return fail(RTA_E_INVALID_ARG, "null pipeline");
+  if (n_pkt < 0 || n_bytes < 0 || pool_elems < 0) return fail(RTA_E_INVALID_ARG, "negative size");
+  if (n_pkt == 0) return RTA_OK;
+  if (n_pkt > 0x7fffffffLL) return fail(RTA_E_SHAPE, "too many packets for one launch");
+  if (!bytes || !pkt_off || !tel_type || !tel_trace_off || (pool_elems > 0 && !pool))
+    return fail(RTA_E_INVALID_ARG, "null pointer");
+  if (!aligned16(bytes) || (pool && !aligned16(pool))) return fail(RTA_E_INVALID_ARG, "bytes and pool must be 16-byte aligned");
+  rta::DecodeArgs da;
+  std::memset(&da, 0, sizeof(da));
+  for (size_t i = 0; i < pipe->cams.size(); ++i) da.cams[i] = pipe->cams[i]->dev;
+  da.n_types = (int32_t)pipe->cams.size();
+  da.bytes = bytes;
+  da.n_bytes = n_bytes;
+  da.pkt_off = pkt_off;
+  da.tel_type = tel_type;
+  da.tel_trace_off = tel_trace_off;
+  da.n_pkt = n_pkt;
+  da.pool = pool;
+  da.pool_elems = pool_elems;
+  da.rec = rec;
+  da.status = pipe->d_status;
+  RTA_HIP(rta::launch_decode(da, (hipStream_t)stream));
   return RTA_OK;
 }
 

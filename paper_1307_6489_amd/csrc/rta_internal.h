@@ -29,7 +29,15 @@ struct DevCam {
   const float* y;          // [Npad] m
   const int16_t* nbr;      // [Npad][8] neighbour indices, -1 padded
   const uint8_t* border;   // [Npad] 1 if fewer than 6 neighbours
+  // Packet CRC constants of this type (multiplications modulo the CRC
+  // polynomial): [0, 256) i*K and [256, 512) i*x^8*K with K = x^(16N), the
+  // per-lane finishing factors x^(8 a_l) at [512, 768), then x^(8*body) and
+  // 0xFFFF * x^(8*(32+body)) at 768 and 769 (body = 2GTN bytes).
+  const uint16_t* crc_tab;
 };
+
+constexpr int kCrcTabLen = 770;
+constexpr int kDecodeNT = 256;  // lanes per packet; one 16-byte column piece each (rows <= 4096 bytes)
 
 // Network parameters, packed (matches RTA_MLP_N_PARAMS): W1 [10][64], b1,
 // W2 [64][64], b2, W3 [64][64], b3, W4 [64][2], b4, with W[in][out].
@@ -69,6 +77,22 @@ struct FusedArgs {
   uint32_t* status;
 };
 
+struct DecodeArgs {
+  DevCam cams[RTA_MAX_TYPES];
+  int32_t n_types;
+  int32_t pad_;
+  const uint8_t* bytes;
+  int64_t n_bytes;
+  const int64_t* pkt_off;
+  int32_t* tel_type;
+  const int64_t* tel_trace_off;
+  int64_t n_pkt;
+  uint16_t* pool;
+  int64_t pool_elems;
+  rta_packet_rec* rec;
+  uint32_t* status;
+};
+
 struct EventArgs {
   rta_boxcut_desc bc;
   MlpDev mlp;
@@ -102,6 +126,7 @@ hipError_t launch_clean(const DevCam& c, const int32_t* D, const uint8_t* gain, 
                         hipStream_t st);
 hipError_t launch_hillas(const DevCam& c, const int32_t* D, const uint8_t* gain, const float* t,
                          const uint8_t* mask, int64_t n_evt, rta_hillas_rec* out, hipStream_t st);
+hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
 hipError_t launch_queue_reset(unsigned long long* queue, hipStream_t st);
 hipError_t launch_fused(const FusedArgs& a, const rta_schedule& s, int n_cu, hipStream_t st);
 hipError_t launch_event(const EventArgs& a, hipStream_t st);
