@@ -282,6 +282,7 @@ rta_status rta_graph_destroy(rta_graph* g);
  *  end  u16  CRC-16 of every byte before it: polynomial x^16+x^12+x^5+1,
  *            register 0xFFFF, most significant bit first, no final xor.
  * ------------------------------------------------------------------------ */
+#define RTA_PACKET_PAD 32          /* readable bytes required after a packet stream */
 #define RTA_PKT_HEADER_BAD 0x1u  /* fixed fields, flags or length inconsistent */
 #define RTA_PKT_TYPE_BAD 0x2u    /* camera type unknown / dimensions differ / no pool slot */
 #define RTA_PKT_CRC_BAD 0x4u     /* CRC mismatch */
@@ -319,7 +320,8 @@ rta_status rta_frame_packets(const rta_camera_info* types, int32_t n_types, cons
  * gets tel_type[p] = -1 (in place: the fused batch then flags it as a bad
  * descriptor), its record's flags and RTA_STATUS_BAD_PACKET in the status
  * word; a CRC failure is known only after its slot was written.
- * bytes: 16-byte aligned.  rec: [n_pkt], NULLABLE. */
+ * bytes: 16-byte aligned, and the RTA_PACKET_PAD bytes after bytes[n_bytes]
+ * must be readable (their content is ignored).  rec: [n_pkt], NULLABLE. */
 rta_status rta_decode_packets(rta_pipeline* pipe, const uint8_t* bytes, int64_t n_bytes, const int64_t* pkt_off,
                               int32_t* tel_type, const int64_t* tel_trace_off, int64_t n_pkt, uint16_t* pool,
                               int64_t pool_elems, rta_packet_rec* rec, rta_stream stream);

@@ -412,14 +412,32 @@ def frame_packets(cams, data, cap=None):
     return off[:k].copy(), ty[:k].copy(), toff[:k].copy(), pool.value, used.value
 
 
-def decode_packets(pipe, data, pkt_off, tel_type, tel_trace_off, pool_elems, pool=None, stream=None, want_rec=True):
+PACKET_PAD = 32
+
+
+def packet_buffer(host_bytes, device):
+    """A device copy of a host packet stream with the RTA_PACKET_PAD readable
+    bytes the decode needs after it.  Returns (tensor, n_bytes)."""
+    import torch
+    h = np.ascontiguousarray(host_bytes, np.uint8).reshape(-1)
+    t = torch.zeros(h.size + PACKET_PAD, dtype=torch.uint8, device=device)
+    t[:h.size].copy_(torch.from_numpy(h))
+    return t, h.size
+
+
+def decode_packets(pipe, data, pkt_off, tel_type, tel_trace_off, pool_elems, pool=None, stream=None, want_rec=True,
+                   n_bytes=None):
     """Device decode of framed packets: ``data`` uint8 device tensor (16-byte
-    aligned), ``pkt_off`` / ``tel_trace_off`` int64 and ``tel_type`` int32
-    device tensors (tel_type is rewritten in place: -1 for rejected packets).
-    Returns (pool uint16 tensor, packet records [n][8] float32-viewed tensor
-    or None)."""
+    aligned) holding the stream in its first ``n_bytes`` bytes (default
+    data.numel() - PACKET_PAD) and at least PACKET_PAD more; ``pkt_off`` /
+    ``tel_trace_off`` int64 and ``tel_type`` int32 device tensors (tel_type is
+    rewritten in place: -1 for rejected packets).  Returns (pool uint16
+    tensor, packet records [n][8] float32-viewed tensor or None)."""
     import torch
     _require(data, torch.uint8, name="data")
+    n_bytes = data.numel() - PACKET_PAD if n_bytes is None else int(n_bytes)
+    if n_bytes < 0 or data.numel() < n_bytes + PACKET_PAD:
+        raise ValueError("data must hold the stream and %d readable bytes after it" % PACKET_PAD)
     _require(pkt_off, torch.int64, name="pkt_off")
     _require(tel_type, torch.int32, name="tel_type")
     _require(tel_trace_off, torch.int64, name="tel_trace_off")
@@ -429,7 +447,7 @@ def decode_packets(pipe, data, pkt_off, tel_type, tel_trace_off, pool_elems, poo
     if pool is None:
         pool = torch.empty(max(int(pool_elems), 8), dtype=torch.uint16, device=data.device)
     rec = torch.empty((n, 8), dtype=torch.float32, device=data.device) if want_rec else None
-    _check(lib().rta_decode_packets(pipe.handle, _ptr(data), data.numel(), _ptr(pkt_off), _ptr(tel_type),
+    _check(lib().rta_decode_packets(pipe.handle, _ptr(data), n_bytes, _ptr(pkt_off), _ptr(tel_type),
                                     _ptr(tel_trace_off), n, _ptr(pool), int(pool_elems), _ptr(rec),
                                     _stream(stream)))
     return pool, rec

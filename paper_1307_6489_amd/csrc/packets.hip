@@ -89,7 +89,11 @@ __global__ __launch_bounds__(kDecodeNT) void k_decode_packets(DecodeArgs a) {
   // header: 32 bytes at po (every lane, uniform)
   const int64_t po = uniform64(a.pkt_off[p]);
   const int64_t base = po & ~int64_t(15);
-  const int64_t avail = a.n_bytes - base;
+  // every load stays below n_bytes + 32 (the caller keeps those 32 bytes
+  // readable): loads are 16-byte pieces at 4-byte aligned addresses, so the
+  // pieces at the end of a packet reach past it into the next packet or the
+  // padding, and a piece straddling the buffer's range would read as zero
+  const int64_t avail = a.n_bytes + kDecodePad - base;
   const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<uint8_t*>(a.bytes + base), 0, (int)(avail > 0x7ffffff0LL ? 0x7ffffff0LL : (avail > 0 ? avail : 0)),
       0x00020000);
@@ -140,27 +144,55 @@ __global__ __launch_bounds__(kDecodeNT) void k_decode_packets(DecodeArgs a) {
     uint16_t* dst = a.pool + slot + 8 * lane;
     uint32_t h = 0;
     uint32_t in = o0 + 32u + lo;
-    for (uint32_t k = 0; k < rows; ++k, in += row) {
-      uint32_t w[4];
-      load16(r, in, w);
-      // CRC share of the piece, two bytes (one sample) per step
-      uint32_t cc = 0;
+    // four rows in flight per lane: loads past the packet's last row read the
+    // next packet or the padding and are ignored
+    constexpr int R = 4;
+    for (uint32_t k0 = 0; k0 < rows; k0 += R, in += R * row) {
+      uint32_t w[R][4];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        if (2 * i < nb) {
-          const uint32_t b0 = (w[i >> 1] >> ((i & 1) * 16)) & 0xFFu, b1 = (w[i >> 1] >> ((i & 1) * 16 + 8)) & 0xFFu;
-          cc = (uint32_t)T1[(cc >> 8) ^ b0] ^ (uint32_t)T0[(cc & 0xFFu) ^ b1];
+      for (int j = 0; j < R; ++j) load16(r, in + (uint32_t)j * row, w[j]);
+      // CRC shares of the R pieces, two bytes (one sample) per step, the R
+      // independent lookup chains interleaved; whole pieces take the
+      // branch-free path, only the last lane of a row can hold fewer bytes
+      uint32_t cc[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) cc[j] = 0;
+      if (nb == 16) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+#pragma unroll
+          for (int j = 0; j < R; ++j) {
+            const uint32_t b0 = (w[j][i >> 1] >> ((i & 1) * 16)) & 0xFFu;
+            const uint32_t b1 = (w[j][i >> 1] >> ((i & 1) * 16 + 8)) & 0xFFu;
+            cc[j] = (uint32_t)T1[(cc[j] >> 8) ^ b0] ^ (uint32_t)T0[(cc[j] & 0xFFu) ^ b1];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          if (2 * i < nb) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+              const uint32_t b0 = (w[j][i >> 1] >> ((i & 1) * 16)) & 0xFFu;
+              const uint32_t b1 = (w[j][i >> 1] >> ((i & 1) * 16 + 8)) & 0xFFu;
+              cc[j] = (uint32_t)T1[(cc[j] >> 8) ^ b0] ^ (uint32_t)T0[(cc[j] & 0xFFu) ^ b1];
+            }
+          }
         }
       }
-      h = (uint32_t)KH[h >> 8] ^ (uint32_t)KL[h & 0xFFu] ^ cc;
-      // big-endian samples -> little-endian, zero beyond the row
-      u32x4 v;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t s = __builtin_amdgcn_perm(w[q], w[q], 0x02030001u);
-        v[q] = 4 * q < nb ? (4 * q + 2 < nb ? s : (s & 0xFFFFu)) : 0u;
+      for (int j = 0; j < R; ++j) {
+        if (k0 + j >= rows) continue;
+        h = (uint32_t)KH[h >> 8] ^ (uint32_t)KL[h & 0xFFu] ^ cc[j];
+        // big-endian samples -> little-endian, zero beyond the row
+        u32x4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t s = __builtin_amdgcn_perm(w[j][q], w[j][q], 0x02030001u);
+          v[q] = 4 * q < nb ? (4 * q + 2 < nb ? s : (s & 0xFFFFu)) : 0u;
+        }
+        if (act) *reinterpret_cast<u32x4*>(dst + (size_t)(k0 + j) * np) = v;
       }
-      if (act) *reinterpret_cast<u32x4*>(dst + (size_t)k * np) = v;
     }
     uint32_t share_l = act ? gf_mul_dev(h, c.crc_tab[512 + lane]) : 0u;
     share_l = wave_xor_last(share_l);

@@ -38,6 +38,7 @@ struct DevCam {
 
 constexpr int kCrcTabLen = 770;
 constexpr int kDecodeNT = 256;  // lanes per packet; one 16-byte column piece each (rows <= 4096 bytes)
+constexpr int kDecodePad = RTA_PACKET_PAD;  // readable bytes required after a packet stream
 
 // Network parameters, packed (matches RTA_MLP_N_PARAMS): W1 [10][64], b1,
 // W2 [64][64], b2, W3 [64][64], b3, W4 [64][2], b4, with W[in][out].

@@ -43,7 +43,8 @@ def decode_both(pool, st, dev):
     pipe = rta.Pipeline(cams, do_stereo=False)
     o, t, po, n, used = rta.frame_packets(cams, st)
     t_dev = to_dev(t, dev)
-    pool_d, rec = rta.decode_packets(pipe, to_dev(st, dev), to_dev(o, dev), t_dev, to_dev(po, dev), n)
+    data, nb = rta.packet_buffer(st, dev)
+    pool_d, rec = rta.decode_packets(pipe, data, to_dev(o, dev), t_dev, to_dev(po, dev), n, n_bytes=nb)
     torch.cuda.synchronize()
     ref_pool, ref_rec, ref_t = op.decode(st, o, t, po, n, types_of(pool))
     g_rec = rec.cpu().numpy().view(rta.PACKET_DTYPE).reshape(-1)
@@ -60,11 +61,15 @@ def compare(pool_d, t_dev, g_rec, ref_pool, ref_rec, ref_t, n):
     return g_pool
 
 
-def test_decode_mixed_stream(torch_dev):
-    pool = W.c1_pool(60, seed=1)
+@pytest.mark.parametrize("n_pk", [60, 61])
+def test_decode_mixed_stream(torch_dev, n_pk):
+    """Both stream-length phases: 61 packets leave the stream 2 bytes past a
+    4-byte boundary, so the last CRC field ends inside a dword (read through
+    the padding after the stream)."""
+    pool = W.c1_pool(n_pk, seed=1)
     order = np.random.default_rng(4).permutation(pool.n)
     st, off = gp.serialize(pool, order, seed=2)
-    say("decode: 60 packets of the 1:3:6 mix, %.1f MB" % (st.size / 1e6))
+    say("decode: %d packets of the 1:3:6 mix, %.1f MB, length mod 4 = %d" % (n_pk, st.size / 1e6, st.size % 4))
     pipe, cams, fr, pool_d, t_dev, g_rec, ref_pool, ref_rec, ref_t = decode_both(pool, st, torch_dev)
     g_pool = compare(pool_d, t_dev, g_rec, ref_pool, ref_rec, ref_t, fr[3])
     assert np.array_equal(g_pool, ref_pool)
@@ -142,7 +147,8 @@ def test_decode_large_stream_sampled(torch_dev):
     pipe = rta.Pipeline(cams, do_stereo=False)
     o, t, po, n, used = rta.frame_packets(cams, st)
     t_dev = to_dev(t, torch_dev)
-    pool_d, rec = rta.decode_packets(pipe, to_dev(st, torch_dev), to_dev(o, torch_dev), t_dev, to_dev(po, torch_dev), n)
+    data, nb = rta.packet_buffer(st, torch_dev)
+    pool_d, rec = rta.decode_packets(pipe, data, to_dev(o, torch_dev), t_dev, to_dev(po, torch_dev), n, n_bytes=nb)
     torch.cuda.synchronize()
     g_rec = rec.cpu().numpy().view(rta.PACKET_DTYPE).reshape(-1)
     assert not g_rec["flags"].any() and pipe.status() == 0
