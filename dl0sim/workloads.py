@@ -132,3 +132,31 @@ def replicate_array_events(aw: ArrayWorkload, n_evt: int, seed: int):
     rel = np.arange(evt_tel_off[-1], dtype=np.int64) - np.repeat(evt_tel_off[:-1], mult)
     tel_src = np.repeat(lo, mult) + rel
     return evt_tel_off, aw.tel_type[tel_src].astype(np.int32), aw.tel_off[tel_src].astype(np.int64), src
+
+
+def sam_events(seed: int, duration_s: float, bkg_rate_hz: float, fov_rad: float, sources=(),
+               gamma_frac_bkg: float = 0.1, invalid_frac: float = 0.02):
+    """Synthetic event list for the alert monitor: background events uniform
+    in time and in a disc of radius fov_rad, with a gamma-like fraction
+    gamma_frac_bkg; sources = [(x, y, t_start, t_end, rate_hz, psf_rad)]
+    add gamma-like events around (x, y) (Gaussian spread psf_rad) during
+    [t_start, t_end).  Returns (time float64, dir float32 [n][2], gammaness
+    float32, stereo-valid bool), sorted by time."""
+    rng = np.random.default_rng(seed)
+    nb = rng.poisson(bkg_rate_hz * duration_s)
+    t = [rng.uniform(0.0, duration_s, nb)]
+    r = fov_rad * np.sqrt(rng.uniform(0.0, 1.0, nb))
+    ph = rng.uniform(0.0, 2.0 * np.pi, nb)
+    d = [np.stack([r * np.cos(ph), r * np.sin(ph)], 1)]
+    g = [np.where(rng.uniform(0.0, 1.0, nb) < gamma_frac_bkg, rng.uniform(0.7, 1.0, nb), rng.uniform(0.0, 0.5, nb))]
+    for (x, y, t_a, t_b, rate, psf) in sources:
+        ns = rng.poisson(rate * (t_b - t_a))
+        t.append(rng.uniform(t_a, t_b, ns))
+        d.append(np.stack([x + psf * rng.standard_normal(ns), y + psf * rng.standard_normal(ns)], 1))
+        g.append(rng.uniform(0.75, 1.0, ns))
+    t = np.concatenate(t)
+    d = np.concatenate(d).astype(np.float32)
+    g = np.concatenate(g).astype(np.float32)
+    valid = rng.uniform(0.0, 1.0, len(t)) >= invalid_frac
+    order = np.argsort(t, kind="stable")
+    return t[order], d[order], g[order], valid[order]
