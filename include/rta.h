@@ -117,6 +117,7 @@ typedef struct rta_camera rta_camera;
 typedef struct rta_pipeline rta_pipeline;
 typedef struct rta_graph rta_graph;
 typedef struct rta_mlp rta_mlp;
+typedef struct rta_sam rta_sam;
 
 /* Camera type description.  All pointers are HOST memory, read during
  * rta_camera_create only (copied to device tables). */
@@ -405,6 +406,73 @@ rta_status rta_classify(rta_mlp* m, const rta_boxcut_desc* bc, const rta_hillas_
  * size-weighted mean score and log10 E to the event record.  The network must
  * outlive the pipeline or be detached first.  bc: HOST memory. */
 rta_status rta_pipeline_attach_mlp(rta_pipeline* pipe, rta_mlp* m, const rta_boxcut_desc* bc);
+
+/* ------------------------------------------------------------------------
+ * Science alert monitor (SAM): search of the event list for transients on
+ * several integration timescales, inside a source region and anywhere in the
+ * field of view (paper, Section 2 requirement (ii) and Section 4.2).
+ *   selection    array events with a valid stereo direction and gammaness
+ *                >= gamma_cut
+ *   binning      time bin b = floor((t - t0) / bin_s) in [0, n_bins); sky
+ *                cell ix = floor(dir_x / cell + grid / 2), iy likewise, in
+ *                [0, grid) (nominal frame, radians; evaluated in FP64)
+ *   counts       C[b][iy][ix] = selected events
+ *   window       for w bins ending at bin e: W = sum of C over e-w < b <= e
+ *   on / off     per cell: N_on = sum of W over the cells at squared cell
+ *                distance <= r_on^2, N_off over r_in^2 < d^2 <= r_out^2,
+ *                both inside the grid; alpha = on cells / off cells
+ *   significance Li & Ma (1983) eq. 17 with the sign of N_on - alpha N_off,
+ *                0 when the excess is exactly zero (decided in integers),
+ *                when N_on + N_off = 0 or without off cells; FP64
+ *   alert        significance >= sigma_alert
+ * ------------------------------------------------------------------------ */
+#define RTA_SAM_MAX_GRID 256
+#define RTA_SAM_MAX_SCALES 8
+#define RTA_SAM_MAX_REACH 16   /* r_out in cells */
+
+typedef struct rta_sam_params {
+  int32_t grid;          /* cells per side, 1..RTA_SAM_MAX_GRID */
+  int32_t n_bins;        /* time bins held, >= 1 (counts: n_bins * grid^2 int32) */
+  double t0;             /* start of bin 0, s */
+  double bin_s;          /* bin width, s, > 0 */
+  float cell;            /* cell size, radians, > 0 */
+  float r_on, r_in, r_out;  /* radii in cells: 0 <= r_on < r_in < r_out <= RTA_SAM_MAX_REACH */
+  float gamma_cut;       /* minimum gammaness */
+  float sigma_alert;     /* alert threshold */
+  int32_t n_scales;      /* 1..RTA_SAM_MAX_SCALES */
+  int32_t scales[RTA_SAM_MAX_SCALES];  /* window lengths in bins, 1..n_bins */
+} rta_sam_params;
+
+/* One alert, 32 bytes. */
+typedef struct rta_sam_alert {
+  int32_t scale;         /* index into scales */
+  int32_t ix, iy;        /* cell */
+  int32_t n_on;
+  double significance;
+  int32_t n_off;
+  int32_t pad_;
+} rta_sam_alert;
+
+/* Create / destroy a monitor on the current device (allocates the counts
+ * and window maps; counts start at zero). */
+rta_status rta_sam_create(const rta_sam_params* params, rta_sam** out);
+rta_status rta_sam_destroy(rta_sam* sam);
+/* Zero the counts (a fill kernel, so it may be captured in a graph). */
+rta_status rta_sam_clear(rta_sam* sam, rta_stream stream);
+/* Add n events to the counts: evt [n] records (DEVICE), t [n] arrival
+ * times in s (DEVICE, FP64).  Events outside the bins or the grid are
+ * ignored.  Order-independent (integer atomics). */
+rta_status rta_sam_fill(rta_sam* sam, const rta_event_rec* evt, const double* t, int64_t n, rta_stream stream);
+/* Search the windows ending at bin end_bin (0 <= end_bin < n_bins) for every
+ * timescale.  significance [n_scales][grid][grid] FP64, n_on / n_off
+ * [n_scales][grid][grid] int32 (each NULLABLE, DEVICE); alerts [max_alerts]
+ * (DEVICE) in any order, n_alerts (DEVICE int32) the number found (may exceed
+ * max_alerts; only max_alerts are written). */
+rta_status rta_sam_search(rta_sam* sam, int32_t end_bin, double* significance, int32_t* n_on, int32_t* n_off,
+                          rta_sam_alert* alerts, int32_t max_alerts, int32_t* n_alerts, rta_stream stream);
+/* Copy the counts [n_bins][grid][grid] int32 into dst (DEVICE, caller-owned),
+ * asynchronously on stream. */
+rta_status rta_sam_counts(const rta_sam* sam, int32_t* dst, rta_stream stream);
 
 #ifdef __cplusplus
 }

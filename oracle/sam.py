@@ -54,18 +54,24 @@ def li_ma_cells(n_on, n_off, c_on, c_off):
     return li_ma(n_on, n_off, c_on / c_off)
 
 
+def f32(v):
+    """The float parameters (cell, radii, cuts) are 32-bit in the interface."""
+    return float(np.float32(v))
+
+
 def histogram(evt_dir, evt_time, gammaness, valid, p):
     """Counts cube [n_bins][grid][grid] (int64) and the number of selected
     events that fell inside it."""
     G, nb = p["grid"], p["n_bins"]
+    cell, cut = f32(p["cell"]), np.float32(p["gamma_cut"])
     C = np.zeros((nb, G, G), np.int64)
     used = 0
     for k in range(len(evt_time)):
-        if not valid[k] or not (gammaness[k] >= p["gamma_cut"]):
+        if not valid[k] or not (np.float32(gammaness[k]) >= cut):
             continue
         b = math.floor((float(evt_time[k]) - p["t0"]) / p["bin_s"])
-        ix = math.floor(float(evt_dir[k, 0]) / p["cell"] + G / 2)
-        iy = math.floor(float(evt_dir[k, 1]) / p["cell"] + G / 2)
+        ix = math.floor(float(evt_dir[k, 0]) / cell + G / 2)
+        iy = math.floor(float(evt_dir[k, 1]) / cell + G / 2)
         if 0 <= b < nb and 0 <= ix < G and 0 <= iy < G:
             C[b, iy, ix] += 1
             used += 1
@@ -81,8 +87,9 @@ def search(C, end_bin, p):
     """Per timescale: significance map [G][G], N_on, N_off, alpha maps, and
     the alerts [(scale index, ix, iy, S)]."""
     G = p["grid"]
-    r_on2, r_in2, r_out2 = p["r_on"] ** 2, p["r_in"] ** 2, p["r_out"] ** 2
-    reach = int(math.ceil(p["r_out"]))
+    r_on2, r_in2, r_out2 = f32(p["r_on"]) ** 2, f32(p["r_in"]) ** 2, f32(p["r_out"]) ** 2
+    reach = int(math.ceil(f32(p["r_out"])))
+    thr = f32(p["sigma_alert"])
     out = []
     alerts = []
     for si, w in enumerate(p["scales"]):
@@ -109,7 +116,7 @@ def search(C, end_bin, p):
                 alpha = con / coff if coff else 0.0
                 s = li_ma_cells(non, noff, con, coff)
                 S[y, x], Non[y, x], Noff[y, x], A[y, x] = s, non, noff, alpha
-                if s >= p["sigma_alert"]:
+                if s >= thr:
                     alerts.append((si, x, y, s))
         out.append({"S": S, "N_on": Non, "N_off": Noff, "alpha": A})
     return out, alerts

@@ -91,6 +91,17 @@ PACKET_DTYPE = np.dtype([("event_number", "<u8"), ("coarse_time", "<u4"), ("fine
                          ("seq_count", "<u2"), ("cam_type", "<u2"), ("flags", "<u4"), ("crc_stored", "<u2"),
                          ("crc_computed", "<u2"), ("pad_", "<u4")])
 
+SAM_ALERT_DTYPE = np.dtype([("scale", "<i4"), ("ix", "<i4"), ("iy", "<i4"), ("n_on", "<i4"),
+                            ("significance", "<f8"), ("n_off", "<i4"), ("pad_", "<i4")])
+
+
+class SamParams(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("n_bins", ctypes.c_int32), ("t0", ctypes.c_double),
+                ("bin_s", ctypes.c_double), ("cell", ctypes.c_float), ("r_on", ctypes.c_float),
+                ("r_in", ctypes.c_float), ("r_out", ctypes.c_float), ("gamma_cut", ctypes.c_float),
+                ("sigma_alert", ctypes.c_float), ("n_scales", ctypes.c_int32), ("scales", ctypes.c_int32 * 8)]
+
+
 # C symbols declared in include/rta.h: name -> (argtypes, restype)
 _vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
 SYMBOLS = {
@@ -116,6 +127,12 @@ SYMBOLS = {
     "rta_graph_capture": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "rta_graph_launch": ([_vp, _vp], ctypes.c_int),
     "rta_graph_destroy": ([_vp], ctypes.c_int),
+    "rta_sam_create": ([_vp, _vp], ctypes.c_int),
+    "rta_sam_destroy": ([_vp], ctypes.c_int),
+    "rta_sam_clear": ([_vp, _vp], ctypes.c_int),
+    "rta_sam_fill": ([_vp, _vp, _vp, _i64, _vp], ctypes.c_int),
+    "rta_sam_search": ([_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp], ctypes.c_int),
+    "rta_sam_counts": ([_vp, _vp, _vp], ctypes.c_int),
     "rta_frame_packets": ([_vp, _i32, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "rta_decode_packets": ([_vp, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_mlp_create": ([_vp, _vp], ctypes.c_int),
@@ -451,6 +468,63 @@ def decode_packets(pipe, data, pkt_off, tel_type, tel_trace_off, pool_elems, poo
                                     _ptr(tel_trace_off), n, _ptr(pool), int(pool_elems), _ptr(rec),
                                     _stream(stream)))
     return pool, rec
+
+
+class Sam:
+    """Science alert monitor: time-binned sky counts of selected events and
+    the Li & Ma search on several timescales (definitions in rta.h)."""
+
+    def __init__(self, grid, n_bins, t0, bin_s, cell, r_on, r_in, r_out, gamma_cut, sigma_alert, scales):
+        sc = (ctypes.c_int32 * 8)(*(list(scales) + [1] * (8 - len(scales))))
+        self.params = SamParams(grid, n_bins, t0, bin_s, cell, r_on, r_in, r_out, gamma_cut, sigma_alert,
+                                len(scales), sc)
+        h = ctypes.c_void_p()
+        _check(lib().rta_sam_create(ctypes.byref(self.params), ctypes.byref(h)))
+        self.handle = h
+        self.grid, self.n_bins, self.scales = grid, n_bins, list(scales)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.rta_sam_destroy(h)
+            self.handle = None
+
+    def clear(self, stream=None):
+        _check(lib().rta_sam_clear(self.handle, _stream(stream)))
+
+    def fill(self, evt, t, stream=None):
+        """evt: event records [n][8] float32 tensor; t: float64 times [n]."""
+        import torch
+        _require(t, torch.float64, name="t")
+        n = t.numel()
+        _require(evt, torch.float32, (n, 8), "evt")
+        _check(lib().rta_sam_fill(self.handle, _ptr(evt), _ptr(t), n, _stream(stream)))
+
+    def counts(self, stream=None):
+        """Copy of the counts cube [n_bins][grid][grid] (int32 numpy)."""
+        import torch
+        out = torch.empty((self.n_bins, self.grid, self.grid), dtype=torch.int32, device="cuda")
+        _check(lib().rta_sam_counts(self.handle, _ptr(out), _stream(stream)))
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+    def search(self, end_bin, max_alerts=4096, stream=None, maps=True):
+        """Significance / N_on / N_off maps [n_scales][grid][grid] (tensors, or
+        None) and the alerts (numpy, sorted by scale, iy, ix)."""
+        import torch
+        dev = torch.device("cuda")
+        shape = (len(self.scales), self.grid, self.grid)
+        sig = torch.empty(shape, dtype=torch.float64, device=dev) if maps else None
+        non = torch.empty(shape, dtype=torch.int32, device=dev) if maps else None
+        noff = torch.empty(shape, dtype=torch.int32, device=dev) if maps else None
+        al = torch.empty((max(max_alerts, 1), 4), dtype=torch.float64, device=dev)
+        cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+        _check(lib().rta_sam_search(self.handle, int(end_bin), _ptr(sig), _ptr(non), _ptr(noff), _ptr(al),
+                                    int(max_alerts), _ptr(cnt), _stream(stream)))
+        k = min(int(cnt.cpu()[0]), max_alerts)
+        a = al.cpu().numpy().view(SAM_ALERT_DTYPE).reshape(-1)[:k]
+        a = a[np.lexsort((a["ix"], a["iy"], a["scale"]))]
+        return sig, non, noff, a, int(cnt.cpu()[0])
 
 
 class Graph:

@@ -31,6 +31,12 @@ struct rta_pipeline {
   hipStream_t capture_stream = nullptr;
 };
 
+struct rta_sam {
+  rta::SamDev dev{};
+  void* dmem = nullptr;
+  int device = 0;
+};
+
 struct rta_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -510,6 +516,112 @@ rta_status rta_decode_packets(rta_pipeline* pipe, const uint8_t* bytes, int64_t 
   da.rec = rec;
   da.status = pipe->d_status;
   RTA_HIP(rta::launch_decode(da, (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_sam_create(const rta_sam_params* p, rta_sam** out) {
+  if (!p || !out) return fail(RTA_E_INVALID_ARG, "null parameters or output handle");
+  *out = nullptr;
+  if (p->grid < 1 || p->grid > RTA_SAM_MAX_GRID) return fail(RTA_E_SHAPE, "grid must be in [1, RTA_SAM_MAX_GRID]");
+  if (p->n_bins < 1) return fail(RTA_E_SHAPE, "n_bins must be >= 1");
+  if ((int64_t)p->n_bins * p->grid * p->grid > 0x7fffffffLL) return fail(RTA_E_SHAPE, "counts cube too large");
+  if (!(p->bin_s > 0.0) || !std::isfinite(p->t0) || !std::isfinite(p->bin_s))
+    return fail(RTA_E_INVALID_ARG, "bin_s must be > 0 and t0 finite");
+  if (!(p->cell > 0.f) || !std::isfinite(p->cell)) return fail(RTA_E_INVALID_ARG, "cell must be > 0");
+  if (!(p->r_on >= 0.f && p->r_on < p->r_in && p->r_in < p->r_out && p->r_out <= (float)RTA_SAM_MAX_REACH))
+    return fail(RTA_E_INVALID_ARG, "radii must satisfy 0 <= r_on < r_in < r_out <= RTA_SAM_MAX_REACH");
+  if (!std::isfinite(p->gamma_cut) || !std::isfinite(p->sigma_alert))
+    return fail(RTA_E_INVALID_ARG, "cuts must be finite");
+  if (p->n_scales < 1 || p->n_scales > RTA_SAM_MAX_SCALES) return fail(RTA_E_SHAPE, "n_scales out of range");
+  for (int k = 0; k < p->n_scales; ++k)
+    if (p->scales[k] < 1 || p->scales[k] > p->n_bins) return fail(RTA_E_SHAPE, "scale must be in [1, n_bins]");
+  // disc and ring offsets, classified in FP64 from the float radii
+  std::vector<int32_t> offs;
+  const double on2 = (double)p->r_on * p->r_on, in2 = (double)p->r_in * p->r_in, out2 = (double)p->r_out * p->r_out;
+  const int reach = (int)std::ceil(p->r_out);
+  for (int dy = -reach; dy <= reach; ++dy)
+    for (int dx = -reach; dx <= reach; ++dx) {
+      const double d2 = (double)(dx * dx + dy * dy);
+      const int kind = d2 <= on2 ? 1 : (d2 > in2 && d2 <= out2 ? 2 : 0);
+      if (kind) offs.push_back((dx + 128) | ((dy + 128) << 8) | (kind << 16));
+    }
+  const size_t G2 = (size_t)p->grid * p->grid;
+  const size_t oC = 0, oW = round256((size_t)p->n_bins * G2 * 4), oO = oW + round256((size_t)p->n_scales * G2 * 4);
+  const size_t total = oO + round256(offs.size() * 4);
+  rta_sam* sam = new (std::nothrow) rta_sam();
+  if (!sam) return fail(RTA_E_NOMEM, "host allocation failed");
+  if (hipGetDevice(&sam->device) != hipSuccess || hipMalloc(&sam->dmem, total) != hipSuccess) {
+    delete sam;
+    return fail(RTA_E_NOMEM, "device allocation for the monitor failed");
+  }
+  uint8_t* base = static_cast<uint8_t*>(sam->dmem);
+  if (hipMemcpy(base + oO, offs.data(), offs.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(sam->dmem);
+    delete sam;
+    return fail(RTA_E_HIP, "copy of the offset table failed");
+  }
+  rta::SamDev& d = sam->dev;
+  d.grid = p->grid;
+  d.n_bins = p->n_bins;
+  d.n_scales = p->n_scales;
+  d.n_offs = (int32_t)offs.size();
+  d.t0 = p->t0;
+  d.bin_s = p->bin_s;
+  d.cell = p->cell;
+  d.gamma_cut = p->gamma_cut;
+  d.sigma_alert = p->sigma_alert;
+  d.r_on2 = (float)on2;
+  for (int k = 0; k < RTA_SAM_MAX_SCALES; ++k) d.scales[k] = k < p->n_scales ? p->scales[k] : 1;
+  d.counts = reinterpret_cast<int32_t*>(base + oC);
+  d.win = reinterpret_cast<int32_t*>(base + oW);
+  d.offs = reinterpret_cast<const int32_t*>(base + oO);
+  if (rta::launch_sam_clear(d, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(sam->dmem);
+    delete sam;
+    return fail(RTA_E_HIP, "clearing the counts failed");
+  }
+  *out = sam;
+  return RTA_OK;
+}
+
+rta_status rta_sam_destroy(rta_sam* sam) {
+  if (!sam) return RTA_OK;
+  if (sam->dmem) (void)hipFree(sam->dmem);
+  delete sam;
+  return RTA_OK;
+}
+
+rta_status rta_sam_clear(rta_sam* sam, rta_stream stream) {
+  if (!sam) return fail(RTA_E_INVALID_ARG, "null monitor");
+  RTA_HIP(rta::launch_sam_clear(sam->dev, (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_sam_fill(rta_sam* sam, const rta_event_rec* evt, const double* t, int64_t n, rta_stream stream) {
+  if (!sam) return fail(RTA_E_INVALID_ARG, "null monitor");
+  if (n < 0) return fail(RTA_E_INVALID_ARG, "negative event count");
+  if (n == 0) return RTA_OK;
+  if (n > 0x7fffffffLL * 256) return fail(RTA_E_SHAPE, "too many events for one launch");
+  if (!evt || !t) return fail(RTA_E_INVALID_ARG, "null events or times");
+  RTA_HIP(rta::launch_sam_fill(sam->dev, evt, t, n, (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_sam_search(rta_sam* sam, int32_t end_bin, double* significance, int32_t* n_on, int32_t* n_off,
+                          rta_sam_alert* alerts, int32_t max_alerts, int32_t* n_alerts, rta_stream stream) {
+  if (!sam) return fail(RTA_E_INVALID_ARG, "null monitor");
+  if (end_bin < 0 || end_bin >= sam->dev.n_bins) return fail(RTA_E_INVALID_ARG, "end_bin out of range");
+  if (max_alerts < 0 || (max_alerts > 0 && !alerts) || !n_alerts)
+    return fail(RTA_E_INVALID_ARG, "null alert outputs");
+  RTA_HIP(rta::launch_sam_search(sam->dev, end_bin, significance, n_on, n_off, alerts, max_alerts, n_alerts,
+                                 (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_sam_counts(const rta_sam* sam, int32_t* dst, rta_stream stream) {
+  if (!sam || !dst) return fail(RTA_E_INVALID_ARG, "null monitor or output");
+  const size_t bytes = (size_t)sam->dev.n_bins * sam->dev.grid * sam->dev.grid * 4;
+  RTA_HIP(hipMemcpyAsync(dst, sam->dev.counts, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return RTA_OK;
 }
 

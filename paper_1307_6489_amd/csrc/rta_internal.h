@@ -94,6 +94,17 @@ struct DecodeArgs {
   uint32_t* status;
 };
 
+// Science alert monitor state on the device.
+struct SamDev {
+  int32_t grid, n_bins, n_scales, n_offs;
+  double t0, bin_s;
+  float cell, gamma_cut, sigma_alert, r_on2;
+  int32_t scales[RTA_SAM_MAX_SCALES];
+  int32_t* counts;      // [n_bins][grid][grid]
+  int32_t* win;         // [n_scales][grid][grid] window sums
+  const int32_t* offs;  // [n_offs] disc / ring offsets: (dx + 128) | (dy + 128) << 8 | kind << 16 (1 on, 2 off)
+};
+
 struct EventArgs {
   rta_boxcut_desc bc;
   MlpDev mlp;
@@ -128,6 +139,10 @@ hipError_t launch_clean(const DevCam& c, const int32_t* D, const uint8_t* gain, 
 hipError_t launch_hillas(const DevCam& c, const int32_t* D, const uint8_t* gain, const float* t,
                          const uint8_t* mask, int64_t n_evt, rta_hillas_rec* out, hipStream_t st);
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
+hipError_t launch_sam_clear(const SamDev& d, hipStream_t st);
+hipError_t launch_sam_fill(const SamDev& d, const rta_event_rec* evt, const double* t, int64_t n, hipStream_t st);
+hipError_t launch_sam_search(const SamDev& d, int end_bin, double* sig, int32_t* n_on, int32_t* n_off,
+                             rta_sam_alert* alerts, int max_alerts, int32_t* n_alerts, hipStream_t st);
 hipError_t launch_queue_reset(unsigned long long* queue, hipStream_t st);
 hipError_t launch_fused(const FusedArgs& a, const rta_schedule& s, int n_cu, hipStream_t st);
 hipError_t launch_event(const EventArgs& a, hipStream_t st);

@@ -1,0 +1,145 @@
+// HIP kernels of the science alert monitor for gfx950 (CDNA4).
+//
+// The real-time analysis searches its event list for transients on several
+// integration timescales, in a source region and anywhere in the field of
+// view (paper, Section 2 requirement (ii); Section 4.2).  The definitions are
+// in rta.h.  Three small data-parallel steps:
+//   fill     one thread per event: selection, FP64 time bin and sky cell,
+//            an integer atomic increment of the counts cube (exact and
+//            independent of the order of events);
+//   window   one thread per (timescale, cell): the sum of the cell's counts
+//            over the window's bins (consecutive threads read consecutive
+//            cells of a bin);
+//   search   one thread per (timescale, cell): on-disc and background-ring
+//            sums over a host-built offset list, alpha from the cell counts
+//            inside the grid, the Li & Ma significance in FP64 with the zero
+//            excess decided in integers, alerts appended through an atomic
+//            counter.
+#include <cmath>
+
+#include "rta_internal.h"
+
+namespace rta {
+namespace {
+
+__global__ void k_sam_clear(int32_t* counts, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    counts[i] = 0;
+}
+
+__global__ void k_sam_fill(SamDev d, const rta_event_rec* __restrict__ evt, const double* __restrict__ t,
+                           int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const rta_event_rec e = evt[k];
+  if (e.flags & RTA_EVT_STEREO_INVALID) return;
+  if (!(e.gammaness >= d.gamma_cut)) return;
+  const double fb = floor((t[k] - d.t0) / d.bin_s);
+  const double half = 0.5 * (double)d.grid;
+  const double fx = floor((double)e.dir_x / (double)d.cell + half);
+  const double fy = floor((double)e.dir_y / (double)d.cell + half);
+  if (!(fb >= 0.0 && fb < (double)d.n_bins && fx >= 0.0 && fx < (double)d.grid && fy >= 0.0 &&
+        fy < (double)d.grid))
+    return;
+  const int64_t G = d.grid;
+  atomicAdd(&d.counts[((int64_t)fb * G + (int64_t)fy) * G + (int64_t)fx], 1);
+}
+
+__global__ void k_sam_window(SamDev d, int end_bin) {
+  const int64_t G2 = (int64_t)d.grid * d.grid;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G2 * d.n_scales) return;
+  const int s = (int)(i / G2);
+  const int64_t cell = i - s * G2;
+  const int lo = max(end_bin - d.scales[s] + 1, 0);
+  int32_t acc = 0;
+  for (int b = lo; b <= end_bin; ++b) acc += d.counts[(int64_t)b * G2 + cell];
+  d.win[i] = acc;
+}
+
+__device__ double li_ma(int64_t n_on, int64_t n_off, int64_t c_on, int64_t c_off) {
+  if (c_off <= 0 || n_on * c_off == c_on * n_off) return 0.0;
+  const double on = (double)n_on, off = (double)n_off, alpha = (double)c_on / (double)c_off;
+  const double tot = on + off;
+  const double t1 = n_on > 0 ? on * log((1.0 + alpha) / alpha * on / tot) : 0.0;
+  const double t2 = n_off > 0 ? off * log((1.0 + alpha) * off / tot) : 0.0;
+  const double v = fmax(2.0 * (t1 + t2), 0.0);
+  return copysign(sqrt(v), on - alpha * off);
+}
+
+__global__ void k_sam_search(SamDev d, double* __restrict__ sig, int32_t* __restrict__ non_out,
+                             int32_t* __restrict__ noff_out, rta_sam_alert* __restrict__ alerts, int max_alerts,
+                             int32_t* n_alerts) {
+  const int G = d.grid;
+  const int64_t G2 = (int64_t)G * G;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G2 * d.n_scales) return;
+  const int s = (int)(i / G2);
+  const int cell = (int)(i - s * G2);
+  const int y = cell / G, x = cell - y * G;
+  const int32_t* W = d.win + s * G2;
+  int64_t n_on = 0, n_off = 0, c_on = 0, c_off = 0;
+  for (int k = 0; k < d.n_offs; ++k) {
+    const int32_t o = d.offs[k];
+    const int xx = x + (o & 0xFF) - 128, yy = y + ((o >> 8) & 0xFF) - 128;
+    if (xx < 0 || xx >= G || yy < 0 || yy >= G) continue;
+    const int32_t v = W[(int64_t)yy * G + xx];
+    if ((o >> 16) == 1) {
+      n_on += v;
+      ++c_on;
+    } else {
+      n_off += v;
+      ++c_off;
+    }
+  }
+  const double S = li_ma(n_on, n_off, c_on, c_off);
+  if (sig) sig[i] = S;
+  if (non_out) non_out[i] = (int32_t)n_on;
+  if (noff_out) noff_out[i] = (int32_t)n_off;
+  if (S >= (double)d.sigma_alert) {
+    const int slot = atomicAdd(n_alerts, 1);
+    if (slot < max_alerts) {
+      rta_sam_alert a;
+      a.scale = s;
+      a.ix = x;
+      a.iy = y;
+      a.n_on = (int32_t)n_on;
+      a.significance = S;
+      a.n_off = (int32_t)n_off;
+      a.pad_ = 0;
+      alerts[slot] = a;
+    }
+  }
+}
+
+__global__ void k_zero_i32(int32_t* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
+unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) / nt); }
+
+}  // namespace
+
+hipError_t launch_sam_clear(const SamDev& d, hipStream_t st) {
+  const int64_t n = (int64_t)d.n_bins * d.grid * d.grid;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_sam_clear, dim3((unsigned)blocks), dim3(256), 0, st, d.counts, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sam_fill(const SamDev& d, const rta_event_rec* evt, const double* t, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_sam_fill, dim3(blocks_for(n, 256)), dim3(256), 0, st, d, evt, t, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sam_search(const SamDev& d, int end_bin, double* sig, int32_t* n_on, int32_t* n_off,
+                             rta_sam_alert* alerts, int max_alerts, int32_t* n_alerts, hipStream_t st) {
+  const int64_t n = (int64_t)d.n_scales * d.grid * d.grid;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, n_alerts);
+  hipLaunchKernelGGL(k_sam_window, dim3(blocks_for(n, 256)), dim3(256), 0, st, d, end_bin);
+  hipLaunchKernelGGL(k_sam_search, dim3(blocks_for(n, 256)), dim3(256), 0, st, d, sig, n_on, n_off, alerts,
+                     max_alerts, n_alerts);
+  return hipGetLastError();
+}
+
+}  // namespace rta
