@@ -408,6 +408,50 @@ rta_status rta_classify(rta_mlp* m, const rta_boxcut_desc* bc, const rta_hillas_
 rta_status rta_pipeline_attach_mlp(rta_pipeline* pipe, rta_mlp* m, const rta_boxcut_desc* bc);
 
 /* ------------------------------------------------------------------------
+ * Real-time health monitor: a basic quality check of the acquired data that
+ * tells the alert monitor when the data are not good (paper, Section 4.2).
+ * Over n_evt camera events of one type, per gain g and pixel i:
+ *   n = n_evt * T samples, s1 = sum x, s2 = sum x^2, n_sat = samples >= the
+ *   saturation level (the high-gain switch level for the high gain of a
+ *   dual-gain camera, 65535 otherwise); mean = s1 / n, rms = sqrt(max(s2 / n
+ *   - mean^2, 0)) in FP64 without contraction; per gain the lower median of
+ *   the pixels' rms (element (N-1)/2 of the sorted values); flags
+ *   RTA_HEALTH_DEAD rms < rms_dead, RTA_HEALTH_NOISY rms > noisy_factor *
+ *   median, RTA_HEALTH_PED_SHIFT |mean - P/256| > ped_tol (P the Q8
+ *   pedestal), RTA_HEALTH_SATURATING n_sat > sat_frac * n; verdict 1 when
+ *   the pixels with any flag in any gain exceed bad_frac_max * N.
+ * ------------------------------------------------------------------------ */
+#define RTA_HEALTH_DEAD 0x1u
+#define RTA_HEALTH_NOISY 0x2u
+#define RTA_HEALTH_PED_SHIFT 0x4u
+#define RTA_HEALTH_SATURATING 0x8u
+
+typedef struct rta_health_params {
+  float rms_dead, noisy_factor, ped_tol, sat_frac, bad_frac_max;
+  int32_t pad_;
+} rta_health_params;
+
+/* Per pixel and gain, 64 bytes. */
+typedef struct rta_pixel_health {
+  uint64_t n, s1, s2, n_sat;
+  double mean, rms;
+  uint32_t flags, pad_;
+  uint64_t reserved_;
+} rta_pixel_health;
+
+typedef struct rta_camera_health {
+  double median_rms[2];  /* per gain (index 1 unused for single gain) */
+  int32_t n_bad;         /* pixels with any flag */
+  int32_t verdict;       /* 1: data not good */
+} rta_camera_health;
+
+/* Health statistics of n_evt events of one type: traces [n_evt][G][T][Npad]
+ * (DEVICE), pix [G][N] and out (DEVICE).  Uses accumulators owned by the
+ * camera: calls on one camera must not overlap. */
+rta_status rta_health(rta_camera* cam, const uint16_t* traces, int64_t n_evt, const rta_health_params* params,
+                      rta_pixel_health* pix, rta_camera_health* out, rta_stream stream);
+
+/* ------------------------------------------------------------------------
  * Science alert monitor (SAM): search of the event list for transients on
  * several integration timescales, inside a source region and anywhere in the
  * field of view (paper, Section 2 requirement (ii) and Section 4.2).

@@ -91,6 +91,17 @@ PACKET_DTYPE = np.dtype([("event_number", "<u8"), ("coarse_time", "<u4"), ("fine
                          ("seq_count", "<u2"), ("cam_type", "<u2"), ("flags", "<u4"), ("crc_stored", "<u2"),
                          ("crc_computed", "<u2"), ("pad_", "<u4")])
 
+PIXEL_HEALTH_DTYPE = np.dtype([("n", "<u8"), ("s1", "<u8"), ("s2", "<u8"), ("n_sat", "<u8"), ("mean", "<f8"),
+                               ("rms", "<f8"), ("flags", "<u4"), ("pad_", "<u4"), ("reserved_", "<u8")])
+CAMERA_HEALTH_DTYPE = np.dtype([("median_rms", "<f8", (2,)), ("n_bad", "<i4"), ("verdict", "<i4")])
+HEALTH_DEAD, HEALTH_NOISY, HEALTH_PED_SHIFT, HEALTH_SATURATING = 0x1, 0x2, 0x4, 0x8
+
+
+class HealthParams(ctypes.Structure):
+    _fields_ = [("rms_dead", ctypes.c_float), ("noisy_factor", ctypes.c_float), ("ped_tol", ctypes.c_float),
+                ("sat_frac", ctypes.c_float), ("bad_frac_max", ctypes.c_float), ("pad_", ctypes.c_int32)]
+
+
 SAM_ALERT_DTYPE = np.dtype([("scale", "<i4"), ("ix", "<i4"), ("iy", "<i4"), ("n_on", "<i4"),
                             ("significance", "<f8"), ("n_off", "<i4"), ("pad_", "<i4")])
 
@@ -127,6 +138,7 @@ SYMBOLS = {
     "rta_graph_capture": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "rta_graph_launch": ([_vp, _vp], ctypes.c_int),
     "rta_graph_destroy": ([_vp], ctypes.c_int),
+    "rta_health": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
     "rta_sam_create": ([_vp, _vp], ctypes.c_int),
     "rta_sam_destroy": ([_vp], ctypes.c_int),
     "rta_sam_clear": ([_vp, _vp], ctypes.c_int),
@@ -468,6 +480,24 @@ def decode_packets(pipe, data, pkt_off, tel_type, tel_trace_off, pool_elems, poo
                                     _ptr(tel_trace_off), n, _ptr(pool), int(pool_elems), _ptr(rec),
                                     _stream(stream)))
     return pool, rec
+
+
+def health(cam: Camera, traces, rms_dead=0.5, noisy_factor=3.0, ped_tol=20.0, sat_frac=0.01, bad_frac_max=0.05,
+           stream=None, to_host=True):
+    """Health statistics of the events of ``traces`` (uint16 [E][G][T][Npad],
+    one camera type).  Returns (per-pixel records [G][N], camera summary) as
+    numpy records, or the device tensors with to_host=False."""
+    import torch
+    E = cam._n_evt(traces)
+    p = HealthParams(rms_dead, noisy_factor, ped_tol, sat_frac, bad_frac_max, 0)
+    pix = torch.empty((cam.n_gain * cam.n_pix, 8), dtype=torch.float64, device=traces.device)
+    out = torch.empty(3, dtype=torch.float64, device=traces.device)
+    _check(lib().rta_health(cam.handle, _ptr(traces), E, ctypes.byref(p), _ptr(pix), _ptr(out), _stream(stream)))
+    if not to_host:
+        return pix, out
+    pr = pix.cpu().numpy().view(PIXEL_HEALTH_DTYPE).reshape(cam.n_gain, cam.n_pix)
+    cr = out.cpu().numpy().view(CAMERA_HEALTH_DTYPE)[0]
+    return pr, cr
 
 
 class Sam:

@@ -1,0 +1,213 @@
+// HIP kernels of the real-time health monitor for gfx950 (CDNA4).
+//
+// A basic quality check of the acquired data (paper, Section 4.2): per pixel
+// and gain, the sample count, sum, sum of squares and saturated samples over
+// a batch of camera events of one type, then mean / rms, the camera's median
+// rms and the bad-pixel flags (definitions in rta.h).
+//   accumulate  workgroups take events in turn; each lane owns 8
+//               consecutive pixels and streams their 16-byte slices, keeping
+//               64-bit sums in registers across its events; one integer
+//               atomic per pixel and quantity per workgroup at the end, so
+//               the totals are exact and independent of the schedule;
+//   evaluate    one workgroup: FP64 mean / rms without contraction, a
+//               bitonic sort of the rms in LDS for the lower median, flags,
+//               the bad-pixel count and the verdict.
+#include <cmath>
+
+#include "rta_internal.h"
+
+namespace rta {
+namespace {
+
+constexpr int kHealthNT = 256;
+constexpr int kHealthPPL = 8;
+constexpr int kEvalNT = 1024;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void k_health_zero(uint64_t* acc, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc[i] = 0;
+}
+
+// acc: [3][G][Npad] = s1, s2, n_sat
+__global__ __launch_bounds__(kHealthNT) void k_health_accum(DevCam c, const uint16_t* __restrict__ traces,
+                                                            int64_t n_evt, uint64_t* __restrict__ acc) {
+  const int N = c.n_pix, np = c.n_pix_pad, T = c.n_samp, G = c.n_gain;
+  const int pix0 = (int)threadIdx.x * kHealthPPL;
+  const bool act = pix0 < np;
+  const uint32_t lvl0 = G == 2 ? (uint32_t)c.hg_switch : 65535u;
+  uint64_t s1[2][kHealthPPL], s2[2][kHealthPPL];
+  uint32_t ns[2][kHealthPPL];
+#pragma unroll
+  for (int g = 0; g < 2; ++g)
+#pragma unroll
+    for (int p = 0; p < kHealthPPL; ++p) { s1[g][p] = 0; s2[g][p] = 0; ns[g][p] = 0; }
+  if (act) {
+    for (int64_t e = blockIdx.x; e < n_evt; e += gridDim.x) {
+      const uint16_t* ev = traces + e * c.event_elems;
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        if (g >= G) break;
+        const uint32_t lvl = g == 0 ? lvl0 : 65535u;
+        uint32_t e1[kHealthPPL];
+#pragma unroll
+        for (int p = 0; p < kHealthPPL; ++p) e1[p] = 0;
+        const uint16_t* col = ev + (size_t)g * T * np + pix0;
+        // slices in groups of eight, double buffered: the next group's loads
+        // are in flight while the current group is reduced (slots past T
+        // re-read the last slice and are not accumulated)
+        auto load8 = [&](u32x4 (&d)[8], int k0) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int k = min(k0 + j, T - 1);
+            d[j] = *reinterpret_cast<const u32x4*>(col + (size_t)k * np);
+          }
+        };
+        auto take8 = [&](const u32x4 (&d)[8], int k0) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if (k0 + j >= T) continue;
+#pragma unroll
+            for (int p = 0; p < kHealthPPL; ++p) {
+              const uint32_t x = (d[j][p >> 1] >> ((p & 1) * 16)) & 0xFFFFu;
+              e1[p] += x;
+              s2[g][p] += (uint64_t)(x * x);
+              ns[g][p] += x >= lvl ? 1u : 0u;
+            }
+          }
+        };
+        u32x4 A[8], B[8];
+        load8(A, 0);
+        for (int k0 = 0; k0 < T; k0 += 16) {
+          if (k0 + 8 < T) load8(B, k0 + 8);
+          take8(A, k0);
+          if (k0 + 8 >= T) break;
+          if (k0 + 16 < T) load8(A, k0 + 16);
+          take8(B, k0 + 8);
+        }
+#pragma unroll
+        for (int p = 0; p < kHealthPPL; ++p) s1[g][p] += e1[p];
+      }
+    }
+  }
+  const int64_t plane = (int64_t)G * np;
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    if (g >= G) break;
+#pragma unroll
+    for (int p = 0; p < kHealthPPL; ++p) {
+      const int i = pix0 + p;
+      if (act && i < N) {
+        const int64_t o = (int64_t)g * np + i;
+        atomicAdd((unsigned long long*)&acc[o], (unsigned long long)s1[g][p]);
+        atomicAdd((unsigned long long*)&acc[plane + o], (unsigned long long)s2[g][p]);
+        atomicAdd((unsigned long long*)&acc[2 * plane + o], (unsigned long long)ns[g][p]);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void pixel_stats(uint64_t s1, uint64_t s2, uint64_t n, double& mean, double& rms) {
+#pragma clang fp contract(off)
+  const double dn = (double)n;
+  mean = (double)s1 / dn;
+  const double var = (double)s2 / dn - mean * mean;
+  rms = sqrt(var > 0.0 ? var : 0.0);
+}
+
+__global__ __launch_bounds__(kEvalNT) void k_health_eval(DevCam c, const uint64_t* __restrict__ acc, int64_t n_evt,
+                                                         rta_health_params prm, rta_pixel_health* __restrict__ pix,
+                                                         rta_camera_health* __restrict__ out) {
+  __shared__ double srt[2 * kMaxPix];
+  __shared__ uint32_t bad[kMaxPix];
+  __shared__ int32_t nbad;
+  const int N = c.n_pix, np = c.n_pix_pad, G = c.n_gain;
+  const uint64_t n = (uint64_t)n_evt * (uint64_t)c.n_samp;
+  const int64_t plane = (int64_t)G * np;
+  int M = 1;
+  while (M < N) M <<= 1;
+  for (int i = threadIdx.x; i < N; i += kEvalNT) bad[i] = 0;
+  if (threadIdx.x == 0) nbad = 0;
+  double med[2] = {0.0, 0.0};
+  for (int g = 0; g < G; ++g) {
+    for (int i = threadIdx.x; i < M; i += kEvalNT) {
+      double mean, rms;
+      if (i < N) {
+        pixel_stats(acc[g * np + i], acc[plane + g * np + i], n, mean, rms);
+        srt[i] = rms;
+      } else {
+        srt[i] = INFINITY;
+      }
+    }
+    __syncthreads();
+    // bitonic sort of srt[0, M) ascending
+    for (int k = 2; k <= M; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = threadIdx.x; i < M; i += kEvalNT) {
+          const int l = i ^ j;
+          if (l > i) {
+            const bool up = (i & k) == 0;
+            const double a = srt[i], b = srt[l];
+            if ((a > b) == up) { srt[i] = b; srt[l] = a; }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    med[g] = srt[(N - 1) / 2];
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += kEvalNT) {
+      const int64_t o = (int64_t)g * np + i;
+      const uint64_t a1 = acc[o], a2 = acc[plane + o], a3 = acc[2 * plane + o];
+      double mean, rms;
+      pixel_stats(a1, a2, n, mean, rms);
+      uint32_t f = 0;
+      if (rms < (double)prm.rms_dead) f |= RTA_HEALTH_DEAD;
+      if (rms > (double)prm.noisy_factor * med[g]) f |= RTA_HEALTH_NOISY;
+      const double ped = (double)c.P256[g * np + i] / 256.0;
+      if (fabs(mean - ped) > (double)prm.ped_tol) f |= RTA_HEALTH_PED_SHIFT;
+      if ((double)a3 > (double)prm.sat_frac * (double)n) f |= RTA_HEALTH_SATURATING;
+      rta_pixel_health h;
+      h.n = n;
+      h.s1 = a1;
+      h.s2 = a2;
+      h.n_sat = a3;
+      h.mean = mean;
+      h.rms = rms;
+      h.flags = f;
+      h.pad_ = 0;
+      h.reserved_ = 0;
+      pix[(int64_t)g * N + i] = h;
+      if (f) bad[i] = 1;
+    }
+    __syncthreads();
+  }
+  int mine = 0;
+  for (int i = threadIdx.x; i < N; i += kEvalNT) mine += bad[i] ? 1 : 0;
+  if (mine) atomicAdd(&nbad, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    rta_camera_health r;
+    r.median_rms[0] = med[0];
+    r.median_rms[1] = G == 2 ? med[1] : 0.0;
+    r.n_bad = nbad;
+    r.verdict = (double)nbad > (double)prm.bad_frac_max * (double)N ? 1 : 0;
+    *out = r;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_health(const DevCam& c, const uint16_t* traces, int64_t n_evt, const rta_health_params& p,
+                         uint64_t* acc, rta_pixel_health* pix, rta_camera_health* out, hipStream_t st) {
+  const int64_t n_acc = (int64_t)3 * c.n_gain * c.n_pix_pad;
+  hipLaunchKernelGGL(k_health_zero, dim3((unsigned)((n_acc + 255) / 256)), dim3(256), 0, st, acc, n_acc);
+  // each workgroup takes several events: its sums reach global memory in one
+  // atomic per pixel and quantity, so fewer workgroups mean less contention
+  const int64_t grid = n_evt < 512 ? n_evt : 512;
+  hipLaunchKernelGGL(k_health_accum, dim3((unsigned)grid), dim3(kHealthNT), 0, st, c, traces, n_evt, acc);
+  hipLaunchKernelGGL(k_health_eval, dim3(1), dim3(kEvalNT), 0, st, c, (const uint64_t*)acc, n_evt, p, pix, out);
+  return hipGetLastError();
+}
+
+}  // namespace rta

@@ -14,6 +14,7 @@ struct rta_camera {
   void* dmem = nullptr;
   rta_camera_info info{};
   int device = 0;
+  uint64_t* health_acc = nullptr;  // [3][G][Npad] health accumulators (s1, s2, n_sat), inside dmem
 };
 
 struct rta_pipeline {
@@ -247,7 +248,8 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
   const size_t oA = oTb + round256(Tb.size() * 4), oX = oA + round256(A.size() * 4);
   const size_t oY = oX + round256(X.size() * 4), oN = oY + round256(Y.size() * 4);
   const size_t oB = oN + round256(nb.size() * 2), oC = oB + round256(border.size());
-  const size_t total = oC + round256(crc.size() * 2);
+  const size_t oH = oC + round256(crc.size() * 2);
+  const size_t total = oH + round256((size_t)3 * G * Np * 8);
   std::vector<uint8_t> host(total, 0);
   std::memcpy(host.data() + oP, P.data(), P.size() * 4);
   std::memcpy(host.data() + oTp, Tp.data(), Tp.size() * 4);
@@ -289,6 +291,7 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
   c.nbr = reinterpret_cast<const int16_t*>(base + oN);
   c.border = base + oB;
   c.crc_tab = reinterpret_cast<const uint16_t*>(base + oC);
+  cam->health_acc = reinterpret_cast<uint64_t*>(base + oH);
   cam->info = rta_camera_info{N, Np, T, G, w, d->fixed_start, c.event_elems};
   *out = cam;
   return RTA_OK;
@@ -516,6 +519,21 @@ rta_status rta_decode_packets(rta_pipeline* pipe, const uint8_t* bytes, int64_t 
   da.rec = rec;
   da.status = pipe->d_status;
   RTA_HIP(rta::launch_decode(da, (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_health(rta_camera* cam, const uint16_t* traces, int64_t n_evt, const rta_health_params* params,
+                      rta_pixel_health* pix, rta_camera_health* out, rta_stream stream) {
+  if (!cam || !params) return fail(RTA_E_INVALID_ARG, "null camera or parameters");
+  if (n_evt < 1) return fail(RTA_E_INVALID_ARG, "n_evt must be >= 1");
+  if (n_evt > 0x7fffffffLL) return fail(RTA_E_SHAPE, "too many events for one launch");
+  if (!traces || !aligned16(traces)) return fail(RTA_E_INVALID_ARG, "traces must be non-null and 16-byte aligned");
+  if (!pix || !out) return fail(RTA_E_INVALID_ARG, "null outputs");
+  const float v[5] = {params->rms_dead, params->noisy_factor, params->ped_tol, params->sat_frac,
+                      params->bad_frac_max};
+  for (float x : v)
+    if (!std::isfinite(x)) return fail(RTA_E_INVALID_ARG, "health thresholds must be finite");
+  RTA_HIP(rta::launch_health(cam->dev, traces, n_evt, *params, cam->health_acc, pix, out, (hipStream_t)stream));
   return RTA_OK;
 }
 

@@ -139,6 +139,8 @@ hipError_t launch_clean(const DevCam& c, const int32_t* D, const uint8_t* gain, 
 hipError_t launch_hillas(const DevCam& c, const int32_t* D, const uint8_t* gain, const float* t,
                          const uint8_t* mask, int64_t n_evt, rta_hillas_rec* out, hipStream_t st);
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
+hipError_t launch_health(const DevCam& c, const uint16_t* traces, int64_t n_evt, const rta_health_params& p,
+                         uint64_t* acc, rta_pixel_health* pix, rta_camera_health* out, hipStream_t st);
 hipError_t launch_sam_clear(const SamDev& d, hipStream_t st);
 hipError_t launch_sam_fill(const SamDev& d, const rta_event_rec* evt, const double* t, int64_t n, hipStream_t st);
 hipError_t launch_sam_search(const SamDev& d, int end_bin, double* sig, int32_t* n_on, int32_t* n_off,

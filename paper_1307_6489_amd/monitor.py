@@ -9,6 +9,8 @@ lists (background uniform over the field, flares as point sources):
   search    latency of one search over all timescales for a 64 x 64 and a
             128 x 128 sky grid, 3600 one-second bins, windows of 1 s, 10 s,
             1 min, 10 min and 1 h;
+  health    the health monitor's rate over signal-free 2048 x 128 dual-gain
+            events (bytes of traces per second);
   alerts    a one-hour event list at 1 kHz with three flares, searched every
             10 s as the data arrive: the delay from each flare's start to its
             first alert at its position.
@@ -113,11 +115,39 @@ def alert_delay(dev, log=None):
     return res
 
 
+def health_rate(dev, n_evt=2000, log=None):
+    """rta_health over n_evt signal-free 2048 x 128 dual-gain events."""
+    import torch
+    import dl0sim
+    ct = dl0sim.camera_types_c1()[2]
+    sh = dl0sim.draw_ellipses(dl0sim.draw_cfg_plain(ct.n_samp), 21, 0, 200)
+    sh["size"][:, 0] = 0.0
+    base = dl0sim.render_traces(ct, sh, 21)
+    tr = torch.from_numpy(np.ascontiguousarray(np.tile(base, (n_evt // 200, 1, 1, 1)))).to(dev)
+    cam = rta.Camera.from_type(ct)
+    rta.health(cam, tr)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(5):
+        rta.health(cam, tr, to_host=False)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / 5
+    pix, c = rta.health(cam, tr)
+    r = {"events": n_evt, "GB": tr.numel() * 2 / 1e9, "ms": ms, "GBps": tr.numel() * 2 / (ms * 1e-3) / 1e9,
+         "hbm_frac": tr.numel() * 2 / (ms * 1e-3) / 8e12, "n_bad": int(c["n_bad"]), "verdict": int(c["verdict"])}
+    if log:
+        log("health: %s" % r)
+    return r
+
+
 def main():
     import torch
     dev = torch.device("cuda:0")
     say = lambda s: print(s, flush=True)  # noqa: E731
-    res = {"rates": fill_and_search_rates(dev, say), "alert_delay": alert_delay(dev, say)}
+    res = {"rates": fill_and_search_rates(dev, say), "alert_delay": alert_delay(dev, say),
+           "health": health_rate(dev, log=say)}
     print(json.dumps(res), flush=True)
 
 

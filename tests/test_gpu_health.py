@@ -1,0 +1,74 @@
+"""GPU parity of the health monitor against the oracle: sums and counts
+exact, mean / rms bit-identical (FP64 without contraction on both sides),
+the lower median, flags and the verdict exact."""
+import numpy as np
+import pytest
+
+import dl0sim
+import paper_1307_6489_amd as rta
+from oracle import health as oh
+
+pytestmark = pytest.mark.gpu
+P = {"rms_dead": 0.5, "noisy_factor": 3.0, "ped_tol": 20.0, "sat_frac": 0.01, "bad_frac_max": 0.05}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rta.lib()
+    return torch.device("cuda:0")
+
+
+def check(ct, tr, dev, p=P):
+    import torch
+    cam = rta.Camera.from_type(ct)
+    pix, c = rta.health(cam, torch.from_numpy(np.ascontiguousarray(tr)).to(dev), **p)
+    rp, rc = oh.health(tr, ct.n_pix, ct.n_gain, ct.ped, ct.hg_switch_adc, p)
+    assert np.array_equal(pix["n"].astype(np.int64), rp["n"])
+    for k in ("S1", "S2", "n_sat"):
+        assert np.array_equal(pix[k.lower()].astype(np.int64), rp[k]), k
+    assert np.array_equal(pix["mean"], rp["mean"]) and np.array_equal(pix["rms"], rp["rms"])
+    assert np.array_equal(pix["flags"].astype(np.int64), rp["flags"])
+    assert np.array_equal(c["median_rms"][:ct.n_gain], rc["median_rms"])
+    assert int(c["n_bad"]) == rc["n_bad"] and int(c["verdict"]) == rc["verdict"]
+    return pix, c
+
+
+@pytest.mark.parametrize("ti", [0, 1, 2])
+def test_health_generated_events(torch_dev, ti):
+    ct = dl0sim.camera_types_c1()[ti]
+    say("health:", ct.name, "40 events, seed 17")
+    sh = dl0sim.draw_ellipses(dl0sim.draw_cfg_plain(ct.n_samp), 17, 0, 40)
+    sh["size"][::4, 0] = 1e5           # some saturating bright images
+    tr = dl0sim.render_traces(ct, sh, 17)
+    check(ct, tr, torch_dev)
+
+
+def test_health_planted_faults_and_many_events(torch_dev):
+    """Dead, noisy, shifted and saturating pixels on a single-gain camera,
+    3000 events (several events per workgroup); and random 16-bit data at
+    the largest shape."""
+    ct = dl0sim.CameraType("faulty", 1855, 30, 1, 28.0)
+    sh = dl0sim.draw_ellipses(dl0sim.draw_cfg_plain(30), 18, 0, 3000)
+    sh["size"][:, 0] = 0.0
+    tr = dl0sim.render_traces(ct, sh, 18)
+    tr[:, 0, :, 10] = 301
+    tr[:, 0, :, 20] = np.clip(tr[:, 0, :, 20].astype(np.int64) * 5 - 1200, 0, 65535)
+    tr[:, 0, :, 30] += 60
+    tr[:40, 0, :, 40] = 65535
+    say("health: planted faults, 3000 events")
+    pix, c = check(ct, tr, torch_dev)
+    f = pix["flags"][0]
+    assert f[10] & rta.HEALTH_DEAD and f[20] & rta.HEALTH_NOISY and f[30] & rta.HEALTH_PED_SHIFT
+    assert f[40] & rta.HEALTH_SATURATING
+    big = dl0sim.CameraType("max", 2048, 255, 1, 5.6)
+    rng = np.random.default_rng(2)
+    tr = rng.integers(0, 65536, size=(5, 1, 255, 2048), dtype=np.uint16)
+    say("health: random 2048 x 255")
+    check(big, tr, torch_dev)
