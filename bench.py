@@ -220,7 +220,7 @@ def main():
                          "exactly 2^30 bytes each) to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU; run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
