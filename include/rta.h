@@ -201,7 +201,10 @@ int32_t rta_version(void);
 rta_status rta_device_cus(int32_t* n_cu);
 
 /* Create / destroy a camera type.  Quantises pedestals to Q8 and builds the
- * integer cleaning thresholds and neighbour tables on the current device. */
+ * integer cleaning thresholds and neighbour tables on the current device.
+ * The camera's device memory also holds the health monitor's scratch:
+ * 512 partial blocks of 3 * n_gain * n_pix_pad 64-bit sums (50 MB for a
+ * 2048-pixel dual-gain type). */
 rta_status rta_camera_create(const rta_camera_desc* desc, rta_camera** out);
 rta_status rta_camera_destroy(rta_camera* cam);
 rta_status rta_camera_get_info(const rta_camera* cam, rta_camera_info* info);
@@ -359,7 +362,11 @@ rta_status rta_mlp_get_params(rta_mlp* m, float* params);
 rta_status rta_mlp_forward(rta_mlp* m, const float* x, int64_t B, float* out, rta_stream stream);
 /* Loss and gradient of one batch (B <= max_batch): label [B] (1 gamma, 0
  * hadron), log10e [B] (used for gammas).  grad: device [RTA_MLP_N_PARAMS]
- * (NULLABLE), loss: device scalar (NULLABLE).  Weights are not changed. */
+ * (NULLABLE), loss: device scalar (NULLABLE).  Weights are not changed.
+ * The batch sums run in a fixed order, so equal inputs give bit-equal
+ * results.  loss_grad and train_step use the network's per-batch scratch
+ * and train_step rewrites its weights: issue the calls on one network from
+ * one stream (calls that overlap on the device race). */
 rta_status rta_mlp_loss_grad(rta_mlp* m, const float* x, const float* label, const float* log10e, int64_t B,
                              float* grad, float* loss, rta_stream stream);
 /* One training step: loss_grad then an Adam update of the masters and the

@@ -6,9 +6,11 @@
 // rms and the bad-pixel flags (definitions in rta.h).
 //   accumulate  workgroups take events in turn; each lane owns 8
 //               consecutive pixels and streams their 16-byte slices, keeping
-//               64-bit sums in registers across its events; one integer
-//               atomic per pixel and quantity per workgroup at the end, so
-//               the totals are exact and independent of the schedule;
+//               64-bit sums in registers across its events, and stores them
+//               to its workgroup's partial block at the end;
+//   reduce      per pixel and quantity, the sum of the partial blocks (16
+//               slices of blocks per output, combined in LDS), so the totals
+//               are exact integers independent of the schedule;
 //   evaluate    one workgroup: FP64 mean / rms without contraction, a
 //               bitonic sort of the rms in LDS for the lower median, flags,
 //               the bad-pixel count and the verdict.
@@ -24,14 +26,9 @@ constexpr int kHealthPPL = 8;
 constexpr int kEvalNT = 1024;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-__global__ void k_health_zero(uint64_t* acc, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    acc[i] = 0;
-}
-
-// acc: [3][G][Npad] = s1, s2, n_sat
+// part: [gridDim.x][3][G][Npad] = s1, s2, n_sat of this workgroup's events
 __global__ __launch_bounds__(kHealthNT) void k_health_accum(DevCam c, const uint16_t* __restrict__ traces,
-                                                            int64_t n_evt, uint64_t* __restrict__ acc) {
+                                                            int64_t n_evt, uint64_t* __restrict__ part) {
   const int N = c.n_pix, np = c.n_pix_pad, T = c.n_samp, G = c.n_gain;
   const int pix0 = (int)threadIdx.x * kHealthPPL;
   const bool act = pix0 < np;
@@ -90,20 +87,55 @@ __global__ __launch_bounds__(kHealthNT) void k_health_accum(DevCam c, const uint
       }
     }
   }
+  if (!act) return;
+  // padding pixels (i >= N) store zeros
   const int64_t plane = (int64_t)G * np;
+  uint64_t* __restrict__ dst = part + (int64_t)blockIdx.x * 3 * plane;
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     if (g >= G) break;
 #pragma unroll
     for (int p = 0; p < kHealthPPL; ++p) {
       const int i = pix0 + p;
-      if (act && i < N) {
-        const int64_t o = (int64_t)g * np + i;
-        atomicAdd((unsigned long long*)&acc[o], (unsigned long long)s1[g][p]);
-        atomicAdd((unsigned long long*)&acc[plane + o], (unsigned long long)s2[g][p]);
-        atomicAdd((unsigned long long*)&acc[2 * plane + o], (unsigned long long)ns[g][p]);
-      }
+      const bool real = i < N;
+      const int64_t o = (int64_t)g * np + i;
+      dst[o] = real ? s1[g][p] : 0ull;
+      dst[plane + o] = real ? s2[g][p] : 0ull;
+      dst[2 * plane + o] = real ? (uint64_t)ns[g][p] : 0ull;
     }
+  }
+}
+
+// acc[o] = sum over the n_part partial blocks of part[w][o], o < n_out.  A
+// workgroup owns 16 consecutive outputs; its 16 lane groups sum every 16th
+// block (16 loads in flight per lane), then LDS adds the 16 group sums.
+constexpr int kRedOut = 16, kRedSlices = 16;
+
+__global__ __launch_bounds__(kRedOut * kRedSlices) void k_health_reduce(const uint64_t* __restrict__ part,
+                                                                        int64_t n_out, int n_part,
+                                                                        uint64_t* __restrict__ acc) {
+  __shared__ uint64_t red[kRedSlices][kRedOut];
+  const int ol = threadIdx.x % kRedOut, sl = threadIdx.x / kRedOut;
+  const int64_t o = (int64_t)blockIdx.x * kRedOut + ol;
+  uint64_t s = 0;
+  if (o < n_out) {
+    int w = sl;
+    for (; w + kRedSlices * 15 < n_part; w += kRedSlices * 16) {
+      uint64_t v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = part[(int64_t)(w + kRedSlices * u) * n_out + o];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += v[u];
+    }
+    for (; w < n_part; w += kRedSlices) s += part[(int64_t)w * n_out + o];
+  }
+  red[sl][ol] = s;
+  __syncthreads();
+  if (threadIdx.x < kRedOut && o < n_out) {
+    uint64_t t = 0;
+#pragma unroll
+    for (int k = 0; k < kRedSlices; ++k) t += red[k][threadIdx.x];
+    acc[o] = t;
   }
 }
 
@@ -199,13 +231,15 @@ __global__ __launch_bounds__(kEvalNT) void k_health_eval(DevCam c, const uint64_
 }  // namespace
 
 hipError_t launch_health(const DevCam& c, const uint16_t* traces, int64_t n_evt, const rta_health_params& p,
-                         uint64_t* acc, rta_pixel_health* pix, rta_camera_health* out, hipStream_t st) {
-  const int64_t n_acc = (int64_t)3 * c.n_gain * c.n_pix_pad;
-  hipLaunchKernelGGL(k_health_zero, dim3((unsigned)((n_acc + 255) / 256)), dim3(256), 0, st, acc, n_acc);
-  // each workgroup takes several events: its sums reach global memory in one
-  // atomic per pixel and quantity, so fewer workgroups mean less contention
-  const int64_t grid = n_evt < 512 ? n_evt : 512;
-  hipLaunchKernelGGL(k_health_accum, dim3((unsigned)grid), dim3(kHealthNT), 0, st, c, traces, n_evt, acc);
+                         uint64_t* part, uint64_t* acc, rta_pixel_health* pix, rta_camera_health* out,
+                         hipStream_t st) {
+  const int64_t n_out = (int64_t)3 * c.n_gain * c.n_pix_pad;
+  // each workgroup takes several events; two workgroups per compute unit
+  // keep enough loads in flight
+  const int grid = (int)(n_evt < kHealthParts ? n_evt : kHealthParts);
+  hipLaunchKernelGGL(k_health_accum, dim3((unsigned)grid), dim3(kHealthNT), 0, st, c, traces, n_evt, part);
+  hipLaunchKernelGGL(k_health_reduce, dim3((unsigned)((n_out + kRedOut - 1) / kRedOut)), dim3(kRedOut * kRedSlices),
+                     0, st, (const uint64_t*)part, n_out, grid, acc);
   hipLaunchKernelGGL(k_health_eval, dim3(1), dim3(kEvalNT), 0, st, c, (const uint64_t*)acc, n_evt, p, pix, out);
   return hipGetLastError();
 }

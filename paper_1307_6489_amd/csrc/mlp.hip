@@ -13,8 +13,8 @@
 // the next layer, so activations go from one layer to the next in registers.
 // The backward pass uses the same trick with the untransposed weights.  Weight
 // gradients contract over the batch, so per-row activations and gradients are
-// written feature-major ([F][B], bf16) and one wavefront per 16x16 weight tile
-// runs the batch contraction with the same instruction.
+// written feature-major ([F][B], bf16) and wavefronts, one per 16x16 weight
+// tile and batch slice, run the batch contraction with the same instruction.
 #include <cmath>
 
 #include "mlp_device.h"
@@ -98,13 +98,43 @@ __global__ __launch_bounds__(kRowsNT) void k_mlp_rows(MlpDev w, const float* __r
   }
 }
 
-// Weight / bias gradients and the loss: batch contractions, one wavefront per
-// 16x16 weight tile (40), one per bias vector (4), one for the loss sum.
-constexpr int kGradWaves = 45;
+// Weight / bias gradients and the loss.  The batch contraction of each 16x16
+// weight tile (40) and bias vector (4) is cut into kGradSplit slices of
+// consecutive 16-row blocks, one wavefront per (tile, slice), each writing
+// its partial sums to gpart[slice]; a last wavefront sums the loss.  The
+// slices are added in slice order by grad_sum (fixed order: the gradient is
+// reproducible).  One long contraction per tile would leave the chip nearly
+// idle and every step waiting on the previous load.
+constexpr int kGradTiles = 44;
+constexpr int kGradBlocks = kGradTiles * kGradSplit + 1;
 
 __global__ __launch_bounds__(64) void k_mlp_grad(MlpDev w, int B, int Bpad, float* __restrict__ loss_out) {
-  const int wv = blockIdx.x, lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
-  const int nk = Bpad / 16;
+  const int lane = threadIdx.x, col = lane & 15, grp = lane >> 4;
+  if (blockIdx.x == kGradTiles * kGradSplit) {
+    // 16 loads in flight per step, added in row order
+    float s = 0.f;
+    int r = lane;
+    for (; r + 64 * 15 < B; r += 64 * 16) {
+      float v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = w.loss_row[r + 64 * u];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += v[u];
+    }
+    for (; r < B; r += 64) s += w.loss_row[r];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) {
+      const float L = s / (float)B;
+      if (loss_out) *loss_out = L;
+      w.loss_row[Bpad] = L;
+    }
+    return;
+  }
+  const int wv = blockIdx.x / kGradSplit, sl = blockIdx.x % kGradSplit;
+  const int nk = Bpad / 16, per = (nk + kGradSplit - 1) / kGradSplit;
+  const int k0 = min(nk, sl * per), k1 = min(nk, k0 + per);
+  float* __restrict__ part = w.gpart + (size_t)sl * kNParams;
   if (wv < 40) {
     // tile -> (layer, input chunk, output chunk)
     const uint16_t *H, *G;
@@ -114,14 +144,25 @@ __global__ __launch_bounds__(64) void k_mlp_grad(MlpDev w, int B, int Bpad, floa
     else if (wv < 36) { const int t = wv - 20; H = w.H2; G = w.G3; in0 = 16 * (t / 4); out0 = 16 * (t % 4); in_dim = kHid; out_dim = kHid; off = kOffW3; }
     else { H = w.H3; G = w.G4; in0 = 16 * (wv - 36); out0 = 0; in_dim = kHid; out_dim = kOut; off = kOffW4; }
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < nk; ++k)
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) {  // four 16-row blocks loaded before their MFMAs
+      bf16x4 a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = load4(H, Bpad, in0 + col, 16 * (k + u) + 4 * grp);
+        b[u] = load4(G, Bpad, out0 + col, 16 * (k + u) + 4 * grp);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = mfma(a[u], b[u], acc);
+    }
+    for (; k < k1; ++k)
       acc = mfma(load4(H, Bpad, in0 + col, 16 * k + 4 * grp), load4(G, Bpad, out0 + col, 16 * k + 4 * grp), acc);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int m = in0 + 4 * grp + i, n = out0 + col;
-      if (m < in_dim && n < out_dim) w.grad[off + m * out_dim + n] = acc[i];
+      if (m < in_dim && n < out_dim) part[off + m * out_dim + n] = acc[i];
     }
-  } else if (wv < 44) {
+  } else {
     const int l = wv - 40;  // bias of layer l+1
     const uint16_t* G = l == 0 ? w.G1 : l == 1 ? w.G2 : l == 2 ? w.G3 : w.G4;
     const int nchunk = l == 3 ? 1 : 4, dim = l == 3 ? kOut : kHid;
@@ -130,21 +171,32 @@ __global__ __launch_bounds__(64) void k_mlp_grad(MlpDev w, int B, int Bpad, floa
     ones[0] = ones[1] = ones[2] = ones[3] = (short)0x3F80;  // bf16(1.0)
     for (int c = 0; c < nchunk; ++c) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      for (int k = 0; k < nk; ++k) acc = mfma(ones, load4(G, Bpad, 16 * c + col, 16 * k + 4 * grp), acc);
-      const int n = 16 * c + col;
-      if (grp == 0 && n < dim) w.grad[off + n] = acc[0];
-    }
-  } else {
-    float s = 0.f;
-    for (int r = lane; r < B; r += 64) s += w.loss_row[r];
+      int k = k0;
+      for (; k + 4 <= k1; k += 4) {
+        bf16x4 b[4];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) {
-      const float L = s / (float)B;
-      if (loss_out) *loss_out = L;
-      w.loss_row[Bpad] = L;
+        for (int u = 0; u < 4; ++u) b[u] = load4(G, Bpad, 16 * c + col, 16 * (k + u) + 4 * grp);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = mfma(ones, b[u], acc);
+      }
+      for (; k < k1; ++k) acc = mfma(ones, load4(G, Bpad, 16 * c + col, 16 * k + 4 * grp), acc);
+      const int n = 16 * c + col;
+      if (grp == 0 && n < dim) part[off + n] = acc[0];
     }
   }
+}
+
+// Gradient of parameter p: the slice partials added in slice order.
+__device__ __forceinline__ float grad_sum(const MlpDev& w, int p) {
+  float g = 0.f;
+#pragma unroll
+  for (int s = 0; s < kGradSplit; ++s) g += w.gpart[(size_t)s * kNParams + p];
+  return g;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_grad_sum(MlpDev w) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < kNParams) w.grad[p] = grad_sum(w, p);
 }
 
 // Parameter index -> bf16 copies in both orientations.
@@ -176,15 +228,17 @@ __device__ __forceinline__ void write_bf16_copies(const MlpDev& w, int p, float 
   }
 }
 
-// Adam step on the FP32 master weights (update == 0: only refresh the bf16
-// copies from the masters).  c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t).
+// Adam step on the FP32 master weights with the gradient summed from the
+// slice partials (update == 0: only refresh the bf16 copies from the
+// masters).  c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t).
 __global__ __launch_bounds__(256) void k_mlp_adam(MlpDev w, int update, float lr, float b1, float b2, float eps,
                                                   float c1, float c2) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= kNParams) return;
   float v = w.master[p];
   if (update) {
-    const float g = w.grad[p];
+    const float g = grad_sum(w, p);
+    w.grad[p] = g;
     const float m = b1 * w.m1[p] + (1.f - b1) * g;
     const float s = b2 * w.m2[p] + (1.f - b2) * g * g;
     w.m1[p] = m;
@@ -209,7 +263,12 @@ hipError_t launch_mlp_rows(const MlpDev& w, const float* x, const float* label, 
 }
 
 hipError_t launch_mlp_grad(const MlpDev& w, int B, int Bpad, float* loss_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_mlp_grad, dim3(kGradWaves), dim3(64), 0, st, w, B, Bpad, loss_out);
+  hipLaunchKernelGGL(k_mlp_grad, dim3(kGradBlocks), dim3(64), 0, st, w, B, Bpad, loss_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad_sum(const MlpDev& w, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_grad_sum, dim3((kNParams + 255) / 256), dim3(256), 0, st, w);
   return hipGetLastError();
 }
 

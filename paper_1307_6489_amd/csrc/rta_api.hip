@@ -14,7 +14,8 @@ struct rta_camera {
   void* dmem = nullptr;
   rta_camera_info info{};
   int device = 0;
-  uint64_t* health_acc = nullptr;  // [3][G][Npad] health accumulators (s1, s2, n_sat), inside dmem
+  uint64_t* health_acc = nullptr;   // [3][G][Npad] health totals (s1, s2, n_sat), inside dmem
+  uint64_t* health_part = nullptr;  // [kHealthParts][3][G][Npad] per-workgroup partial sums, inside dmem
 };
 
 struct rta_pipeline {
@@ -249,8 +250,11 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
   const size_t oY = oX + round256(X.size() * 4), oN = oY + round256(Y.size() * 4);
   const size_t oB = oN + round256(nb.size() * 2), oC = oB + round256(border.size());
   const size_t oH = oC + round256(crc.size() * 2);
-  const size_t total = oH + round256((size_t)3 * G * Np * 8);
-  std::vector<uint8_t> host(total, 0);
+  const size_t oHP = oH + round256((size_t)3 * G * Np * 8);
+  const size_t total = oHP + round256((size_t)rta::kHealthParts * 3 * G * Np * 8);
+  // tables are copied from the host; the health scratch after them is
+  // written by the health kernels before it is read
+  std::vector<uint8_t> host(oH, 0);
   std::memcpy(host.data() + oP, P.data(), P.size() * 4);
   std::memcpy(host.data() + oTp, Tp.data(), Tp.size() * 4);
   std::memcpy(host.data() + oTb, Tb.data(), Tb.size() * 4);
@@ -266,7 +270,7 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
     delete cam;
     return fail(RTA_E_NOMEM, "device allocation for camera tables failed");
   }
-  if (hipMemcpy(cam->dmem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMemcpy(cam->dmem, host.data(), oH, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(cam->dmem);
     delete cam;
     return fail(RTA_E_HIP, "copy of camera tables failed");
@@ -292,6 +296,7 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
   c.border = base + oB;
   c.crc_tab = reinterpret_cast<const uint16_t*>(base + oC);
   cam->health_acc = reinterpret_cast<uint64_t*>(base + oH);
+  cam->health_part = reinterpret_cast<uint64_t*>(base + oHP);
   cam->info = rta_camera_info{N, Np, T, G, w, d->fixed_start, c.event_elems};
   *out = cam;
   return RTA_OK;
@@ -533,7 +538,8 @@ rta_status rta_health(rta_camera* cam, const uint16_t* traces, int64_t n_evt, co
                       params->bad_frac_max};
   for (float x : v)
     if (!std::isfinite(x)) return fail(RTA_E_INVALID_ARG, "health thresholds must be finite");
-  RTA_HIP(rta::launch_health(cam->dev, traces, n_evt, *params, cam->health_acc, pix, out, (hipStream_t)stream));
+  RTA_HIP(rta::launch_health(cam->dev, traces, n_evt, *params, cam->health_part, cam->health_acc, pix, out,
+                             (hipStream_t)stream));
   return RTA_OK;
 }
 
@@ -753,6 +759,7 @@ rta_status rta_mlp_create(const rta_mlp_desc* d, rta_mlp** out) {
   const size_t P = rta::kNParams, Bp = (size_t)m->bpad_max;
   // sub-array byte sizes, each rounded to 256
   const size_t sizes[] = {P * 4, P * 4, P * 4, P * 4,                       // master m1 m2 grad
+                          rta::kGradSplit * P * 4,                          // gpart
                           64 * 16 * 2, 64 * 64 * 2, 64 * 64 * 2, 16 * 64 * 2,  // W1t..W4t
                           64 * 64 * 2, 64 * 64 * 2, 64 * 16 * 2,             // W2n..W4n
                           64 * 4, 64 * 4, 64 * 4, 16 * 4, 16 * 4, 16 * 4,     // b1..b4 mean std
@@ -776,6 +783,7 @@ rta_status rta_mlp_create(const rta_mlp_desc* d, rta_mlp** out) {
   int i = 0;
   w.master = (float*)(b + off[i++]); w.m1 = (float*)(b + off[i++]); w.m2 = (float*)(b + off[i++]);
   w.grad = (float*)(b + off[i++]);
+  w.gpart = (float*)(b + off[i++]);
   w.W1t = (uint16_t*)(b + off[i++]); w.W2t = (uint16_t*)(b + off[i++]); w.W3t = (uint16_t*)(b + off[i++]);
   w.W4t = (uint16_t*)(b + off[i++]);
   w.W2n = (uint16_t*)(b + off[i++]); w.W3n = (uint16_t*)(b + off[i++]); w.W4n = (uint16_t*)(b + off[i++]);
@@ -855,6 +863,7 @@ rta_status rta_mlp_loss_grad(rta_mlp* m, const float* x, const float* label, con
                              float* grad, float* loss, rta_stream stream) {
   rta_status s = mlp_loss_grad(m, x, label, log10e, B, loss, (hipStream_t)stream);
   if (s != RTA_OK) return s;
+  RTA_HIP(rta::launch_mlp_grad_sum(m->dev, (hipStream_t)stream));
   if (grad)
     RTA_HIP(hipMemcpyAsync(grad, m->dev.grad, sizeof(float) * rta::kNParams, hipMemcpyDeviceToDevice,
                            (hipStream_t)stream));

@@ -43,6 +43,7 @@ constexpr int kDecodePad = RTA_PACKET_PAD;  // readable bytes required after a p
 // Network parameters, packed (matches RTA_MLP_N_PARAMS): W1 [10][64], b1,
 // W2 [64][64], b2, W3 [64][64], b3, W4 [64][2], b4, with W[in][out].
 constexpr int kNParams = 9154;
+constexpr int kGradSplit = 16;  // batch slices of the weight-gradient contraction
 constexpr int kOffW1 = 0, kOffB1 = 640, kOffW2 = 704, kOffB2 = 4800, kOffW3 = 4864, kOffB3 = 8960;
 constexpr int kOffW4 = 9024, kOffB4 = 9152;
 
@@ -52,6 +53,7 @@ constexpr int kOffW4 = 9024, kOffB4 = 9152;
 // and per-batch scratch (feature-major activations / gradients).
 struct MlpDev {
   float *master, *m1, *m2, *grad;
+  float* gpart;                     // [kGradSplit][kNParams] per-slice partial gradients
   uint16_t *W1t, *W2t, *W3t, *W4t;  // [64][16], [64][64], [64][64], [16][64]
   uint16_t *W2n, *W3n, *W4n;        // [64][64], [64][64], [64][16]
   float *b1, *b2, *b3, *b4;         // [64], [64], [64], [16]
@@ -127,6 +129,7 @@ struct EventArgs {
 hipError_t launch_mlp_rows(const MlpDev& w, const float* x, const float* label, const float* log10e, int B, int Bpad,
                            float* out, bool train, hipStream_t st);
 hipError_t launch_mlp_grad(const MlpDev& w, int B, int Bpad, float* loss_out, hipStream_t st);
+hipError_t launch_mlp_grad_sum(const MlpDev& w, hipStream_t st);
 hipError_t launch_mlp_adam(const MlpDev& w, bool update, float lr, float b1, float b2, float eps, float c1, float c2,
                            hipStream_t st);
 
@@ -139,8 +142,12 @@ hipError_t launch_clean(const DevCam& c, const int32_t* D, const uint8_t* gain, 
 hipError_t launch_hillas(const DevCam& c, const int32_t* D, const uint8_t* gain, const float* t,
                          const uint8_t* mask, int64_t n_evt, rta_hillas_rec* out, hipStream_t st);
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
+// Health accumulation: at most kHealthParts workgroups, each leaving its
+// per-pixel sums in a partial block [3][G][Npad] of the camera's scratch.
+constexpr int kHealthParts = 512;
 hipError_t launch_health(const DevCam& c, const uint16_t* traces, int64_t n_evt, const rta_health_params& p,
-                         uint64_t* acc, rta_pixel_health* pix, rta_camera_health* out, hipStream_t st);
+                         uint64_t* part, uint64_t* acc, rta_pixel_health* pix, rta_camera_health* out,
+                         hipStream_t st);
 hipError_t launch_sam_clear(const SamDev& d, hipStream_t st);
 hipError_t launch_sam_fill(const SamDev& d, const rta_event_rec* evt, const double* t, int64_t n, hipStream_t st);
 hipError_t launch_sam_search(const SamDev& d, int end_bin, double* sig, int32_t* n_on, int32_t* n_off,

@@ -25,9 +25,9 @@ def torch_dev():
     return torch.device("cuda:0")
 
 
-def check(ct, tr, dev, p=P):
+def check(ct, tr, dev, p=P, cam=None):
     import torch
-    cam = rta.Camera.from_type(ct)
+    cam = cam or rta.Camera.from_type(ct)
     pix, c = rta.health(cam, torch.from_numpy(np.ascontiguousarray(tr)).to(dev), **p)
     rp, rc = oh.health(tr, ct.n_pix, ct.n_gain, ct.ped, ct.hg_switch_adc, p)
     assert np.array_equal(pix["n"].astype(np.int64), rp["n"])
@@ -72,3 +72,16 @@ def test_health_planted_faults_and_many_events(torch_dev):
     tr = rng.integers(0, 65536, size=(5, 1, 255, 2048), dtype=np.uint16)
     say("health: random 2048 x 255")
     check(big, tr, torch_dev)
+
+
+def test_health_calls_in_a_row_on_one_camera(torch_dev):
+    """One camera handle, 300 dual-gain events then 7: the second call's
+    totals come from its own workgroups only (the per-workgroup partial
+    blocks of the first, larger call are not summed again)."""
+    ct = dl0sim.camera_types_c1()[1]
+    cam = rta.Camera.from_type(ct)
+    for n, seed in ((300, 19), (7, 20)):
+        say("health: %d events on one camera handle, seed %d" % (n, seed))
+        sh = dl0sim.draw_ellipses(dl0sim.draw_cfg_plain(ct.n_samp), seed, 0, n)
+        sh["size"][::5, 0] = 1e5
+        check(ct, dl0sim.render_traces(ct, sh, seed), torch_dev, cam=cam)
