@@ -7,14 +7,17 @@
 //   fill     one thread per event: selection, FP64 time bin and sky cell,
 //            an integer atomic increment of the counts cube (exact and
 //            independent of the order of events);
-//   window   one thread per (timescale, cell): the sum of the cell's counts
-//            over the window's bins (consecutive threads read consecutive
-//            cells of a bin);
+//   window   one thread per (timescale, 64-bin chunk of the window, cell):
+//            the chunk's sum (16 loads in flight, consecutive threads on
+//            consecutive cells of a bin) added to the window sum with an
+//            integer atomic, so every bin of the longest window is read by
+//            its own thread rather than in one long chain;
 //   search   one thread per (timescale, cell): on-disc and background-ring
 //            sums over a host-built offset list, alpha from the cell counts
 //            inside the grid, the Li & Ma significance in FP64 with the zero
 //            excess decided in integers, alerts appended through an atomic
 //            counter.
+#include <algorithm>
 #include <cmath>
 
 #include "rta_internal.h"
@@ -45,16 +48,37 @@ __global__ void k_sam_fill(SamDev d, const rta_event_rec* __restrict__ evt, cons
   atomicAdd(&d.counts[((int64_t)fb * G + (int64_t)fy) * G + (int64_t)fx], 1);
 }
 
-__global__ void k_sam_window(SamDev d, int end_bin) {
+// Window jobs of one search: the chunks of timescale s are jobs
+// [job0[s], job0[s + 1]), chunk j of it covers bins lo[s] + 64 j .. up to
+// end_bin.
+constexpr int kSamChunk = 64;
+struct SamJobs {
+  int32_t job0[RTA_SAM_MAX_SCALES + 1];
+  int32_t lo[RTA_SAM_MAX_SCALES];
+};
+
+__global__ void k_sam_window(SamDev d, int end_bin, SamJobs jb) {
   const int64_t G2 = (int64_t)d.grid * d.grid;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= G2 * d.n_scales) return;
-  const int s = (int)(i / G2);
-  const int64_t cell = i - s * G2;
-  const int lo = max(end_bin - d.scales[s] + 1, 0);
+  const int64_t job = i / G2;
+  if (job >= jb.job0[d.n_scales]) return;
+  const int64_t cell = i - job * G2;
+  int s = 0;
+  while (job >= jb.job0[s + 1]) ++s;
+  const int b0 = jb.lo[s] + (int)(job - jb.job0[s]) * kSamChunk;
+  const int b1 = min(b0 + kSamChunk, end_bin + 1);
+  const int32_t* __restrict__ src = d.counts + cell;
   int32_t acc = 0;
-  for (int b = lo; b <= end_bin; ++b) acc += d.counts[(int64_t)b * G2 + cell];
-  d.win[i] = acc;
+  int b = b0;
+  for (; b + 16 <= b1; b += 16) {
+    int32_t v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = src[(int64_t)(b + u) * G2];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc += v[u];
+  }
+  for (; b < b1; ++b) acc += src[(int64_t)b * G2];
+  if (acc) atomicAdd(&d.win[s * G2 + cell], acc);
 }
 
 __device__ double li_ma(int64_t n_on, int64_t n_off, int64_t c_on, int64_t c_off) {
@@ -134,9 +158,17 @@ hipError_t launch_sam_fill(const SamDev& d, const rta_event_rec* evt, const doub
 
 hipError_t launch_sam_search(const SamDev& d, int end_bin, double* sig, int32_t* n_on, int32_t* n_off,
                              rta_sam_alert* alerts, int max_alerts, int32_t* n_alerts, hipStream_t st) {
-  const int64_t n = (int64_t)d.n_scales * d.grid * d.grid;
+  const int64_t G2 = (int64_t)d.grid * d.grid, n = (int64_t)d.n_scales * G2;
+  SamJobs jb;
+  jb.job0[0] = 0;
+  for (int s = 0; s < d.n_scales; ++s) {
+    jb.lo[s] = std::max(end_bin - d.scales[s] + 1, 0);
+    jb.job0[s + 1] = jb.job0[s] + (end_bin - jb.lo[s] + kSamChunk) / kSamChunk;
+  }
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, n_alerts);
-  hipLaunchKernelGGL(k_sam_window, dim3(blocks_for(n, 256)), dim3(256), 0, st, d, end_bin);
+  hipLaunchKernelGGL(k_sam_clear, dim3(blocks_for(n, 256)), dim3(256), 0, st, d.win, n);
+  hipLaunchKernelGGL(k_sam_window, dim3(blocks_for(jb.job0[d.n_scales] * G2, 256)), dim3(256), 0, st, d, end_bin,
+                     jb);
   hipLaunchKernelGGL(k_sam_search, dim3(blocks_for(n, 256)), dim3(256), 0, st, d, sig, n_on, n_off, alerts,
                      max_alerts, n_alerts);
   return hipGetLastError();
