@@ -5,15 +5,17 @@
 // a batch of camera events of one type, then mean / rms, the camera's median
 // rms and the bad-pixel flags (definitions in rta.h).
 //   accumulate  workgroups take events in turn; each lane owns 8
-//               consecutive pixels and streams their 16-byte slices, keeping
+//               consecutive pixels and streams their 16-byte slices
+//               (non-temporal loads: the traces are read once), keeping
 //               64-bit sums in registers across its events, and stores them
 //               to its workgroup's partial block at the end;
 //   reduce      per pixel and quantity, the sum of the partial blocks (16
 //               slices of blocks per output, combined in LDS), so the totals
 //               are exact integers independent of the schedule;
 //   evaluate    one workgroup: FP64 mean / rms without contraction, a
-//               bitonic sort of the rms in LDS for the lower median, flags,
-//               the bad-pixel count and the verdict.
+//               bitonic sort of the rms (registers, lane shuffles and LDS)
+//               for the lower median, flags, the bad-pixel count and the
+//               verdict.
 #include <cmath>
 
 #include "rta_internal.h"
@@ -24,6 +26,7 @@ namespace {
 constexpr int kHealthNT = 256;
 constexpr int kHealthPPL = 8;
 constexpr int kEvalNT = 1024;
+constexpr int kWave = 64;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // part: [gridDim.x][3][G][Npad] = s1, s2, n_sat of this workgroup's events
@@ -57,7 +60,7 @@ __global__ __launch_bounds__(kHealthNT) void k_health_accum(DevCam c, const uint
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
             const int k = min(k0 + j, T - 1);
-            d[j] = *reinterpret_cast<const u32x4*>(col + (size_t)k * np);
+            d[j] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(col + (size_t)k * np));
           }
         };
         auto take8 = [&](const u32x4 (&d)[8], int k0) {
@@ -147,78 +150,129 @@ __device__ __forceinline__ void pixel_stats(uint64_t s1, uint64_t s2, uint64_t n
   rms = sqrt(var > 0.0 ? var : 0.0);
 }
 
+// One compare-exchange step of a bitonic sort (ascending overall) for the
+// element at index i against its partner's value p: i ^ j is the partner,
+// (i & k) the direction of the block being merged.
+__device__ __forceinline__ double bitonic_step(double v, double p, int i, int j, int k) {
+  const bool take_min = ((i & j) == 0) == ((i & k) == 0);
+  return take_min ? fmin(v, p) : fmax(v, p);
+}
+
+// Evaluation: thread t owns pixels t and t + 1024 of both gains.  The rms of
+// each gain, padded with +inf to 2048 values, is sorted ascending by a
+// bitonic network on registers: partners within a wavefront (j < 64) by
+// lane shuffles, across wavefronts through LDS, j = 1024 inside the
+// thread; both gains go through the network together.
+static_assert(2 * kEvalNT == kMaxPix, "two pixels per evaluation thread");
+
 __global__ __launch_bounds__(kEvalNT) void k_health_eval(DevCam c, const uint64_t* __restrict__ acc, int64_t n_evt,
                                                          rta_health_params prm, rta_pixel_health* __restrict__ pix,
                                                          rta_camera_health* __restrict__ out) {
-  __shared__ double srt[2 * kMaxPix];
-  __shared__ uint32_t bad[kMaxPix];
+  __shared__ double xch[2][kMaxPix];
+  __shared__ double s_med[2];
   __shared__ int32_t nbad;
   const int N = c.n_pix, np = c.n_pix_pad, G = c.n_gain;
+  const int t = threadIdx.x;
   const uint64_t n = (uint64_t)n_evt * (uint64_t)c.n_samp;
   const int64_t plane = (int64_t)G * np;
-  int M = 1;
-  while (M < N) M <<= 1;
-  for (int i = threadIdx.x; i < N; i += kEvalNT) bad[i] = 0;
-  if (threadIdx.x == 0) nbad = 0;
-  double med[2] = {0.0, 0.0};
-  for (int g = 0; g < G; ++g) {
-    for (int i = threadIdx.x; i < M; i += kEvalNT) {
-      double mean, rms;
-      if (i < N) {
-        pixel_stats(acc[g * np + i], acc[plane + g * np + i], n, mean, rms);
-        srt[i] = rms;
-      } else {
-        srt[i] = INFINITY;
+  if (t == 0) nbad = 0;
+  uint64_t a1[2][2], a2[2][2], a3[2][2];
+  double mean[2][2], rms[2][2], v[2][2];
+#pragma unroll
+  for (int g = 0; g < 2; ++g)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int i = t + kEvalNT * e;
+      a1[g][e] = a2[g][e] = a3[g][e] = 0;
+      mean[g][e] = rms[g][e] = 0.0;
+      v[g][e] = INFINITY;
+      if (g < G && i < N) {
+        const int64_t o = (int64_t)g * np + i;
+        a1[g][e] = acc[o];
+        a2[g][e] = acc[plane + o];
+        a3[g][e] = acc[2 * plane + o];
+        pixel_stats(a1[g][e], a2[g][e], n, mean[g][e], rms[g][e]);
+        v[g][e] = rms[g][e];
       }
     }
-    __syncthreads();
-    // bitonic sort of srt[0, M) ascending
-    for (int k = 2; k <= M; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = threadIdx.x; i < M; i += kEvalNT) {
-          const int l = i ^ j;
-          if (l > i) {
-            const bool up = (i & k) == 0;
-            const double a = srt[i], b = srt[l];
-            if ((a > b) == up) { srt[i] = b; srt[l] = a; }
-          }
+#pragma unroll
+  for (int k = 2; k <= kMaxPix; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      double p[2][2];
+      if (j == kEvalNT) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+          p[g][0] = v[g][1];
+          p[g][1] = v[g][0];
+        }
+      } else if (j >= kWave) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+          xch[g][t] = v[g][0];
+          xch[g][t + kEvalNT] = v[g][1];
         }
         __syncthreads();
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+          for (int e = 0; e < 2; ++e) p[g][e] = xch[g][(t + kEvalNT * e) ^ j];
+        __syncthreads();
+      } else {
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+          for (int e = 0; e < 2; ++e) p[g][e] = __shfl_xor(v[g][e], j, kWave);
       }
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) v[g][e] = bitonic_step(v[g][e], p[g][e], t + kEvalNT * e, j, k);
     }
-    med[g] = srt[(N - 1) / 2];
-    __syncthreads();
-    for (int i = threadIdx.x; i < N; i += kEvalNT) {
-      const int64_t o = (int64_t)g * np + i;
-      const uint64_t a1 = acc[o], a2 = acc[plane + o], a3 = acc[2 * plane + o];
-      double mean, rms;
-      pixel_stats(a1, a2, n, mean, rms);
+  }
+  // lower median: sorted element (N - 1) / 2 of each gain
+  const int mi = (N - 1) / 2;
+#pragma unroll
+  for (int e = 0; e < 2; ++e)
+    if (t + kEvalNT * e == mi) {
+      s_med[0] = v[0][e];
+      s_med[1] = v[1][e];
+    }
+  __syncthreads();
+  const double med[2] = {s_med[0], s_med[1]};
+  int mine = 0;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int i = t + kEvalNT * e;
+    if (i >= N) continue;
+    uint32_t any = 0;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      if (g >= G) break;
       uint32_t f = 0;
-      if (rms < (double)prm.rms_dead) f |= RTA_HEALTH_DEAD;
-      if (rms > (double)prm.noisy_factor * med[g]) f |= RTA_HEALTH_NOISY;
+      if (rms[g][e] < (double)prm.rms_dead) f |= RTA_HEALTH_DEAD;
+      if (rms[g][e] > (double)prm.noisy_factor * med[g]) f |= RTA_HEALTH_NOISY;
       const double ped = (double)c.P256[g * np + i] / 256.0;
-      if (fabs(mean - ped) > (double)prm.ped_tol) f |= RTA_HEALTH_PED_SHIFT;
-      if ((double)a3 > (double)prm.sat_frac * (double)n) f |= RTA_HEALTH_SATURATING;
+      if (fabs(mean[g][e] - ped) > (double)prm.ped_tol) f |= RTA_HEALTH_PED_SHIFT;
+      if ((double)a3[g][e] > (double)prm.sat_frac * (double)n) f |= RTA_HEALTH_SATURATING;
       rta_pixel_health h;
       h.n = n;
-      h.s1 = a1;
-      h.s2 = a2;
-      h.n_sat = a3;
-      h.mean = mean;
-      h.rms = rms;
+      h.s1 = a1[g][e];
+      h.s2 = a2[g][e];
+      h.n_sat = a3[g][e];
+      h.mean = mean[g][e];
+      h.rms = rms[g][e];
       h.flags = f;
       h.pad_ = 0;
       h.reserved_ = 0;
       pix[(int64_t)g * N + i] = h;
-      if (f) bad[i] = 1;
+      any |= f;
     }
-    __syncthreads();
+    mine += any ? 1 : 0;
   }
-  int mine = 0;
-  for (int i = threadIdx.x; i < N; i += kEvalNT) mine += bad[i] ? 1 : 0;
   if (mine) atomicAdd(&nbad, mine);
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     rta_camera_health r;
     r.median_rms[0] = med[0];
     r.median_rms[1] = G == 2 ? med[1] : 0.0;

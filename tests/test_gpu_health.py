@@ -85,3 +85,21 @@ def test_health_calls_in_a_row_on_one_camera(torch_dev):
         sh = dl0sim.draw_ellipses(dl0sim.draw_cfg_plain(ct.n_samp), seed, 0, n)
         sh["size"][::5, 0] = 1e5
         check(ct, dl0sim.render_traces(ct, sh, seed), torch_dev, cam=cam)
+
+
+@pytest.mark.parametrize("n_pix", [1, 7, 100, 1000])
+def test_health_small_cameras(torch_dev, n_pix):
+    """Cameras far below 2048 pixels: the sort pads the rms with +inf, the
+    median is element (N - 1) / 2 of the real pixels.  Dual gain, samples
+    around the pedestal, a dead and a noisy pixel where there is room."""
+    ct = dl0sim.CameraType("small%d" % n_pix, n_pix, 20, 2, 10.0)
+    npad = (n_pix + 7) // 8 * 8
+    rng = np.random.default_rng(n_pix)
+    tr = rng.integers(281, 322, size=(9, 2, 20, npad), dtype=np.uint16)
+    if n_pix > 2:
+        tr[:, :, :, 1] = 301
+        tr[:, 0, :, 2] = rng.integers(151, 452, size=(9, 20), dtype=np.uint16)
+    say("health: %d-pixel dual-gain camera, 9 events" % n_pix)
+    pix, c = check(ct, tr, torch_dev)
+    if n_pix > 2:
+        assert pix["flags"][0][1] & rta.HEALTH_DEAD and pix["flags"][0][2] & rta.HEALTH_NOISY
