@@ -39,6 +39,7 @@ STEREO_INVALID = 1
 EX_SLIDING = 0
 EX_FIXED = 1
 EX_GLOBAL_PEAK = 2
+EX_NEIGHBOUR_PEAK = 3
 
 
 def build(force: bool = True) -> str:
@@ -132,7 +133,7 @@ class Camera:
         self.t_pic, self.t_bnd, self.focal = float(t_pic), float(t_bnd), float(focal)
         self.extractor = int(extractor)
         self.fixed_start = (self.n_samp - self.window) // 2 if fixed_start is None else int(fixed_start)
-        if self.extractor not in (EX_SLIDING, EX_FIXED, EX_GLOBAL_PEAK):
+        if self.extractor not in (EX_SLIDING, EX_FIXED, EX_GLOBAL_PEAK, EX_NEIGHBOUR_PEAK):
             raise ValueError("unknown extractor")
         if not 0 <= self.fixed_start <= self.n_samp - self.window:
             raise ValueError("fixed window outside the trace")

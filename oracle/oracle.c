@@ -13,7 +13,7 @@
  *   window sum       W(s) = sum_{k<w} x[s+k] for every start s in [0, T-w],
  *                    summed directly (no running sum)
  *   window start s*  by the camera's signal extractor (the paper's Section 5
- *                    mentions several extraction algorithms; three are here):
+ *                    mentions several extraction algorithms; four are here):
  *                    sliding      first maximiser of W(s) on the pixel's
  *                                 selected gain
  *                    fixed        s0, the same for every pixel; the gain
@@ -22,6 +22,10 @@
  *                    global peak  first maximiser of C(s) = the sum over all
  *                                 pixels of the raw high-gain W(s), the same
  *                                 for every pixel of the event
+ *                    neighbour    first maximiser of C_i(s) = the sum over
+ *                    peak         the pixel's neighbours of their raw
+ *                                 high-gain W(s) (0 for a pixel without
+ *                                 neighbours, so s* = 0)
  *   pedestal (Q8)    P = nearest-even(256 * ped);  D = 256 * W(s*) - w * P
  *   time numerator   Nt = sum_{k<w} k * (256 * x[s*+k] - P)
  *   charge / time    q = D / (256 * a)  p.e.;  t = s* + Nt / D  (D > 0),
@@ -48,7 +52,7 @@
 
 #define OR_PI 3.14159265358979323846
 
-enum { OR_EX_SLIDING = 0, OR_EX_FIXED = 1, OR_EX_GLOBAL_PEAK = 2 };
+enum { OR_EX_SLIDING = 0, OR_EX_FIXED = 1, OR_EX_GLOBAL_PEAK = 2, OR_EX_NEIGHBOUR_PEAK = 3 };
 
 typedef struct oracle_cam {
   int32_t n_pix, n_pix_pad, n_samp, n_gain;
@@ -149,7 +153,22 @@ void oracle_calibrate_event(const oracle_cam* cam, const uint16_t* ev, oracle_pi
         if (W > best) { best = W; sbest = s; }
       }
     } else {
-      sbest = ex == OR_EX_FIXED ? s0 : sglob;
+      if (ex == OR_EX_NEIGHBOUR_PEAK) {
+        /* the neighbours' raw high-gain windows, summed directly for every
+           start; the first maximiser wins */
+        int64_t cbest = -1;
+        for (int s = 0; s + w <= T; ++s) {
+          int64_t C = 0;
+          for (int m = 0; m < cam->max_nbr; ++m) {
+            const int j = cam->nbr[(int64_t)i * cam->max_nbr + m];
+            if (j < 0) continue;
+            for (int k = 0; k < w; ++k) C += ev[(int64_t)(s + k) * Np + j];
+          }
+          if (C > cbest) { cbest = C; sbest = s; }
+        }
+      } else {
+        sbest = ex == OR_EX_FIXED ? s0 : sglob;
+      }
       best = 0;
       for (int k = 0; k < w; ++k) best += tr[(int64_t)(sbest + k) * Np];
     }

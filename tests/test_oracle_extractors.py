@@ -1,6 +1,7 @@
 """Pins of the oracle's alternative signal extractors (fixed window, global
-peak window) against hand-derived values, reductions to the pinned sliding
-window, locality and translation invariances.  CPU only."""
+peak window, neighbour peak window) against hand-derived values, reductions
+to the pinned sliding window, locality and translation invariances.  CPU
+only."""
 import numpy as np
 import pytest
 
@@ -8,7 +9,7 @@ import dl0sim
 import oracle
 
 P = 0.05
-EX = (oracle.EX_SLIDING, oracle.EX_FIXED, oracle.EX_GLOBAL_PEAK)
+EX = (oracle.EX_SLIDING, oracle.EX_FIXED, oracle.EX_GLOBAL_PEAK, oracle.EX_NEIGHBOUR_PEAK)
 
 
 def cam_of(n_pix, T, G, ped, a, extractor, fixed_start=None, w=4, switch=4000, x=None, y=None):
@@ -204,3 +205,80 @@ def test_unknown_extractor_and_bad_fixed_start_are_rejected():
         cam_of(1, 8, 1, 0.0, 1.0, 7)
     with pytest.raises(ValueError):
         cam_of(1, 8, 1, 0.0, 1.0, oracle.EX_FIXED, fixed_start=5)
+
+
+def test_neighbour_peak_hand_case():
+    """Three pixels in a row (0-1-2 neighbours), T = 10, w = 4, pedestal 0:
+    pixel 0 carries 100 at samples 1..4, pixel 1 500 at 5..8, pixel 2 60 at
+    2..5.  Pixel 0's window follows its one neighbour (pixel 1): s* = 5, where
+    its own samples are 0.  Pixel 1 sums pixels 0 and 2: C(0) = 300 + 120,
+    C(1) = 400 + 180, C(2) = 300 + 240, C(3) = 200 + 180: s* = 1, S = 0.
+    Pixel 2 follows pixel 1: s* = 5, S = 60 (its sample 5)."""
+    T = 10
+    tr = np.zeros((1, 3, T), np.int64)
+    tr[0, 0, 1:5] = 100
+    tr[0, 1, 5:9] = 500
+    tr[0, 2, 2:6] = 60
+    r = cam_of(3, T, 1, 0.0, 1.0, oracle.EX_NEIGHBOUR_PEAK).calibrate(event_of(tr))
+    assert list(r["sstar"]) == [5, 1, 5] and list(r["S"]) == [0, 0, 60]
+    assert list(r["peak"]) == [5, 1, 5]
+
+
+def test_neighbour_peak_without_neighbours_starts_at_zero():
+    """A lone pixel has C(s) = 0 for every s: the first start, 0."""
+    tr = np.array([[[5, 1, 1, 1, 90, 90, 90, 90]]])
+    r = cam_of(1, 8, 1, 0.0, 1.0, oracle.EX_NEIGHBOUR_PEAK).calibrate(event_of(tr))[0]
+    assert int(r["sstar"]) == 0 and int(r["S"]) == 8
+
+
+def test_neighbour_peak_reduces_to_sliding_for_identical_traces():
+    """The same trace in every pixel of a row: C_i(s) = (number of
+    neighbours) x W(s), whose first maximiser is the sliding window's (ties
+    included), so every output is the pinned sliding one."""
+    rng = np.random.default_rng(5)
+    for trial in range(200):
+        T = int(rng.integers(4, 20))
+        N = int(rng.integers(2, 6))
+        tr = np.repeat(rng.integers(0, 4, size=(1, 1, T)), N, axis=1)
+        a = cam_of(N, T, 1, 0.0, 1.0, oracle.EX_NEIGHBOUR_PEAK).calibrate(event_of(tr))
+        b = cam_of(N, T, 1, 0.0, 1.0, oracle.EX_SLIDING).calibrate(event_of(tr))
+        assert a.tobytes() == b.tobytes()
+
+
+def test_neighbour_peak_is_local():
+    """On the 37-pixel hexagon: rewriting every sample of pixel j changes the
+    outputs of j and of its neighbours at most; every other pixel is
+    unchanged."""
+    rng = np.random.default_rng(6)
+    a_ = np.arange(-3, 4)
+    pts = [(a, b) for a in a_ for b in a_ if abs(a) <= 3 and abs(b) <= 3 and abs(a + b) <= 3]
+    x = np.array([P * (a + b / 2) for a, b in pts], np.float32)
+    y = np.array([P * b * np.sqrt(3) / 2 for a, b in pts], np.float32)
+    N, T = len(pts), 24
+    d = np.hypot(x[:, None] - x[None, :], y[:, None] - y[None, :])
+    near = (d < 1.4 * P) & (d > 0)
+    cam = cam_of(N, T, 2, 300.0, 10.0, oracle.EX_NEIGHBOUR_PEAK, x=x, y=y)
+    for trial in range(10):
+        tr = rng.integers(250, 4200, size=(2, N, T))
+        base = cam.calibrate(event_of(tr))
+        j = int(rng.integers(0, N))
+        tr2 = tr.copy()
+        tr2[:, j, :] = rng.integers(0, 65536, size=(2, T))
+        got = cam.calibrate(event_of(tr2))
+        same = ~near[j]
+        same[j] = False
+        assert got[same].tobytes() == base[same].tobytes()
+
+
+def test_neighbour_peak_gain_uses_the_whole_trace():
+    """Dual gain: a saturated high-gain sample anywhere in the pixel's trace
+    switches it (as for the sliding window), and the low gain is integrated
+    at the start the neighbours chose."""
+    T = 16
+    hg = np.zeros((2, T), np.int64)
+    lg = np.zeros((2, T), np.int64)
+    hg[0, 0] = 4095                      # pixel 0 saturates at sample 0
+    lg[0, 9:13] = [7, 8, 9, 10]
+    hg[1, 9:13] = 200                    # pixel 1 (pixel 0's neighbour) peaks at 9
+    r = cam_of(2, T, 2, 0.0, 1.0, oracle.EX_NEIGHBOUR_PEAK).calibrate(event_of([hg, lg]))
+    assert int(r["gain"][0]) == 1 and int(r["sstar"][0]) == 9 and int(r["S"][0]) == 34
