@@ -14,7 +14,7 @@
  *                    S = W(s*); peak = s* + earliest argmax of x[s*..s*+w-1].
  *                    The window start s* comes from the signal extractor
  *                    (the paper's Section 5 plans several extraction
- *                    algorithms on the GPU; three are provided):
+ *                    algorithms on the GPU; four are provided):
  *                    RTA_EXTRACT_SLIDING: the earliest maximiser of W(s) over
  *                      s in [0, T-w] (the default);
  *                    RTA_EXTRACT_FIXED: s* = the camera's fixed_start for
@@ -23,7 +23,11 @@
  *                      nothing outside the window is read;
  *                    RTA_EXTRACT_GLOBAL_PEAK: s* = the earliest maximiser of
  *                      the camera sum over pixels of the raw high-gain W(s),
- *                      common to every pixel of the event.
+ *                      common to every pixel of the event;
+ *                    RTA_EXTRACT_NEIGHBOUR_PEAK: per pixel, s* = the earliest
+ *                      maximiser of the sum over the pixel's neighbours of
+ *                      their raw high-gain W(s) (s* = 0 for a pixel without
+ *                      neighbours); the gain decision as for SLIDING.
  *   Calibration      P = nearest-even(256 * ped) (Q8 fixed point),
  *                    D = 256*S - w*P,  q = D / (256 * adc_per_pe)  [p.e.],
  *                    Nt = sum_{k<w} k*(256*x[s*+k] - P),
@@ -86,6 +90,7 @@ extern "C" {
 #define RTA_EXTRACT_SLIDING 0
 #define RTA_EXTRACT_FIXED 1
 #define RTA_EXTRACT_GLOBAL_PEAK 2
+#define RTA_EXTRACT_NEIGHBOUR_PEAK 3
 
 typedef enum rta_status {
   RTA_OK = 0,

@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "unsupported shape", 3: "HIP 
 EXTRACT_SLIDING = 0       # per pixel: earliest maximiser of the window sum
 EXTRACT_FIXED = 1         # every pixel: the camera's fixed window start
 EXTRACT_GLOBAL_PEAK = 2   # every pixel: earliest maximiser of the camera-summed window
+EXTRACT_NEIGHBOUR_PEAK = 3  # per pixel: earliest maximiser of its neighbours' summed window
 FLAG_HILLAS_INVALID = 0x1
 FLAG_TIME_INVALID = 0x2
 FLAG_LOW_GAIN = 0x4

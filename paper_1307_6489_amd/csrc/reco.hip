@@ -290,7 +290,15 @@ __device__ __forceinline__ uint32_t extract_group(const DevCam& c, __amdgpu_buff
 // Window placement by the other extractors.  They produce the same packed key
 // (S << 8) | (255 - s*) as the sliding window, so every later step is shared.
 // ---------------------------------------------------------------------------
-enum : int { kExSliding = RTA_EXTRACT_SLIDING, kExFixed = RTA_EXTRACT_FIXED, kExGlobal = RTA_EXTRACT_GLOBAL_PEAK };
+enum : int {
+  kExSliding = RTA_EXTRACT_SLIDING,
+  kExFixed = RTA_EXTRACT_FIXED,
+  kExGlobal = RTA_EXTRACT_GLOBAL_PEAK,
+  kExNeighbour = RTA_EXTRACT_NEIGHBOUR_PEAK
+};
+
+// Neighbour peak: high-gain slices staged in LDS this many at a time.
+constexpr int kNbrRows = 4;
 
 // Sums of the W samples from slice s on of every pixel of the group (one
 // load per slice) and, with TRACK_MAX, their packed per-pixel maximum.
@@ -447,12 +455,150 @@ __device__ __forceinline__ int global_start(const uint32_t* rows, int T, int32_t
   return *start;
 }
 
+// Neighbour peak for every pixel of the event: the earliest maximiser of
+// C_i(s) = sum over the neighbours j of i of the raw high-gain window sum
+// W_j(s).  Four high-gain slices at a time are staged in LDS transposed,
+// one 64-bit word of four halfwords per pixel (slices k0..k0+3; word Npad = 0
+// stands in for a missing neighbour), so a pixel's neighbours cost one 8-byte
+// read each per four slices, and the per-slice neighbour sums y(t) come from
+// packed dot products.  The next four slices are loaded while the current
+// ones are used.  Each lane keeps, for each of its pixels, the last
+// W-1 sums to form C(t-W+1), the best key (C << 8) | (255 - s) and the raw
+// high-gain maximum (gain decision on the whole trace, as for the sliding
+// window).  Then the pixel's own W samples at its start on its selected gain
+// give S.  Called by every thread of the block (contains barriers).
+template <int PPL, int W, int NT, class Fn>
+__device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer_rsrc_t r,
+                                                const uint16_t* __restrict__ ev, uint16_t* xrow, Fn&& fn) {
+  static_assert(kNbrRows == 4, "four slices per staged pixel word pair");
+  constexpr int MAXP = (kMaxPix + NT * PPL - 1) / (NT * PPL);
+  const int N = c.n_pix, np = c.n_pix_pad, T = c.n_samp;
+  const bool dual = c.n_gain == 2;
+  const int npass = (N + NT * PPL - 1) / (NT * PPL);
+  // staged words: slices k0, k0+1 in the low dword, k0+2, k0+3 in the high
+  // one (64-bit words: the packed dot of a two-lane vector's second element
+  // has been seen compiled onto its first)
+  uint64_t* xs = reinterpret_cast<uint64_t*>(xrow);
+  // pixel j = 8 g + m of 16-byte group g lives in word m * (Npad / 8) + g,
+  // so the eight words a stager writes land in eight rows of consecutive
+  // words (no bank conflicts between the lanes of a store)
+  const uint32_t g8 = (uint32_t)np / 8u;
+  auto slot = [g8](uint32_t j) { return (j & 7u) * g8 + (j >> 3); };
+  uint32_t nb[MAXP][PPL][3];      // six neighbour indices per pixel, packed int16 (Npad if missing)
+  uint32_t ring[MAXP][PPL][W - 1];
+  uint32_t best[MAXP][PPL], hmax[MAXP][PPL];
+#pragma unroll
+  for (int ps = 0; ps < MAXP; ++ps)
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const int i = (ps * NT + (int)threadIdx.x) * PPL + p;
+      nb[ps][p][0] = nb[ps][p][1] = nb[ps][p][2] = (uint32_t)np * 0x10001u;
+      if (ps < npass && i < N) {
+        const int4 v = *reinterpret_cast<const int4*>(c.nbr + (size_t)i * kNbrCols);
+        const uint32_t w3[3] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z};
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+          const uint32_t lo = (w3[h] & 0x8000u) ? (uint32_t)np : slot(w3[h] & 0xffffu);
+          const uint32_t hi = (w3[h] & 0x80000000u) ? (uint32_t)np : slot(w3[h] >> 16);
+          nb[ps][p][h] = lo | (hi << 16);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < W - 1; ++k) ring[ps][p][k] = 0;
+      best[ps][p] = 0;
+      hmax[ps][p] = 0;
+    }
+  if (threadIdx.x == 0) xs[np] = 0ull;
+  // thread q stages 16-byte pixel group q (np / 8 <= kMaxPix / 8 <= NT
+  // groups), the next four slices loaded while the current ones are used
+  static_assert(kMaxPix / 8 <= NT, "one staged pixel group per thread");
+  const int q = threadIdx.x;
+  const bool stager = q < np / 8;
+  const us2 row_lo = {1, 0}, row_hi = {0, 1};
+  u32x4 d[kNbrRows];
+  auto load4 = [&](int k0) {
+#pragma unroll
+    for (int k = 0; k < kNbrRows; ++k)
+      d[k] = __builtin_amdgcn_raw_buffer_load_b128(r, q * 16, (k0 + k) * np * 2, RTA_TRACE_CPOL);
+  };
+  if (stager) load4(0);
+  for (int k0 = 0; k0 < T; k0 += kNbrRows) {
+    __syncthreads();  // the previous slices are consumed
+    if (stager) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const uint32_t sel = (m & 1) ? 0x07060302u : 0x05040100u;  // high / low halfwords
+        xs[m * g8 + q] = (uint64_t)__builtin_amdgcn_perm(d[1][m >> 1], d[0][m >> 1], sel) |
+                        ((uint64_t)__builtin_amdgcn_perm(d[3][m >> 1], d[2][m >> 1], sel) << 32);
+      }
+    }
+    __syncthreads();
+    if (stager && k0 + kNbrRows < T) load4(k0 + kNbrRows);
+#pragma unroll
+    for (int ps = 0; ps < MAXP; ++ps)
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        const int i = (ps * NT + (int)threadIdx.x) * PPL + p;
+        if (ps >= npass || i >= N) continue;
+        uint32_t y[kNbrRows] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          const int jn = (int)((nb[ps][p][m >> 1] >> ((m & 1) * 16)) & 0xffffu);
+          const uint64_t v = xs[jn];
+          const uint32_t v01 = (uint32_t)v, v23 = (uint32_t)(v >> 32);
+          y[0] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v01), row_lo, y[0], false);
+          y[1] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v01), row_hi, y[1], false);
+          y[2] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v23), row_lo, y[2], false);
+          y[3] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v23), row_hi, y[3], false);
+        }
+        const uint64_t own = xs[slot((uint32_t)i)];
+        const uint32_t o01 = (uint32_t)own, o23 = (uint32_t)(own >> 32);
+        const uint32_t xo[kNbrRows] = {lo16(o01), hi16(o01), lo16(o23), hi16(o23)};
+#pragma unroll
+        for (int k = 0; k < kNbrRows; ++k) {
+          const int t = k0 + k;
+          if (t >= T) break;
+          hmax[ps][p] = max(hmax[ps][p], xo[k]);
+          uint32_t C = y[k];
+#pragma unroll
+          for (int u = 0; u < W - 1; ++u) C += ring[ps][p][u];
+          if (t >= W - 1) best[ps][p] = max(best[ps][p], (C << 8) | (uint32_t)(255 - (t - (W - 1))));
+#pragma unroll
+          for (int u = W - 2; u > 0; --u) ring[ps][p][u] = ring[ps][p][u - 1];
+          ring[ps][p][0] = y[k];
+        }
+      }
+  }
+#pragma unroll
+  for (int ps = 0; ps < MAXP; ++ps) {
+    if (ps >= npass) continue;
+    const int pix0 = (ps * NT + (int)threadIdx.x) * PPL;
+    uint32_t sw = 0, key[PPL];
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const int i = pix0 + p;
+      key[p] = 0;
+      if (i >= N) continue;
+      const int g = dual && (int)hmax[ps][p] >= c.hg_switch ? 1 : 0;
+      sw |= (uint32_t)g << p;
+      const int s = 255 - (int)(best[ps][p] & 255u);
+      const uint16_t* col = ev + ((size_t)g * T + s) * np + i;
+      uint32_t S = 0;
+#pragma unroll
+      for (int k = 0; k < W; ++k) S += col[(size_t)k * np];
+      key[p] = (S << 8) | (uint32_t)(255 - s);
+    }
+    fn(pix0, key, sw);
+  }
+}
+
 // Keys of every pixel of one event, group by group: fn(pix0, key, sw) for
 // each of this thread's groups.  rows / start: LDS scratch of the global
-// peak (NT/64 * 256 words, one word).
+// peak (NT/64 * 256 words, one word); xrow: LDS slices of the neighbour
+// peak (kNbrRows * (kMaxPix + 8) halfwords).
 template <int EX, int PPL, int W, int CH, int NT, class Fn>
-__device__ __forceinline__ void extract_event(const DevCam& c, __amdgpu_buffer_rsrc_t r, uint32_t* rows,
-                                              int32_t* start, Fn&& fn) {
+__device__ __forceinline__ void extract_event(const DevCam& c, __amdgpu_buffer_rsrc_t r, const uint16_t* ev,
+                                              uint32_t* rows, int32_t* start, uint16_t* xrow, Fn&& fn) {
   const int N = c.n_pix, np = c.n_pix_pad, T = c.n_samp;
   const bool dual = c.n_gain == 2;
   // Uniform pass loop: every lane streams (loads past the event read 0 from
@@ -469,6 +615,8 @@ __device__ __forceinline__ void extract_event(const DevCam& c, __amdgpu_buffer_r
         sw = fixed_group<PPL, W>(c, r, pix0, np, T, dual, key);
       fn(pix0, key, sw);
     }
+  } else if constexpr (EX == kExNeighbour) {
+    neighbour_event<PPL, W, NT>(c, r, ev, xrow, fn);
   } else {
     constexpr int MAXP = (kMaxPix + NT * PPL - 1) / (NT * PPL);
     uint32_t* my_rows = rows + (threadIdx.x / kWave) * 256;
@@ -545,7 +693,10 @@ struct TelSmem {
     float q[kMaxPix];        // charge per slot, p.e.
     uint32_t rows[kMaxPix];  // global peak: per-wave slice sums (extraction only)
   };
-  double t[kMaxPix];         // peak time per slot, samples
+  union alignas(16) {        // 16-byte aligned: slices are staged with 16-byte stores
+    double t[kMaxPix];       // peak time per slot, samples
+    uint16_t xrow[kNbrRows * (kMaxPix + 8)];  // neighbour peak: staged slices + zero slot (extraction only)
+  };
   double red[16 * 8];        // cross-wave reduction scratch
   int32_t start;             // global peak window start
 };
@@ -589,7 +740,8 @@ __device__ __forceinline__ int extract_phase(const DevCam& c, const uint16_t* __
   const int N = c.n_pix, np = c.n_pix_pad;
   const __amdgpu_buffer_rsrc_t r = event_rsrc(ev, c.event_elems);
   int nlow = 0;
-  extract_event<EX, PPL, W, CH, NT>(c, r, sm.rows, &sm.start, [&](int pix0, const uint32_t (&key)[PPL], uint32_t sw) {
+  extract_event<EX, PPL, W, CH, NT>(c, r, ev, sm.rows, &sm.start, sm.xrow, [&](int pix0, const uint32_t (&key)[PPL],
+                                                                                uint32_t sw) {
     if (pix0 >= N) return;
     int32_t P[PPL], Tb[PPL], Tp[PPL];
     load_i32<PPL>(P, c.P256 + pix0);
@@ -869,13 +1021,15 @@ __global__ __launch_bounds__(NT) void k_calibrate(DevCam c, const uint16_t* __re
                                                   int32_t* D, uint8_t* sstar, uint8_t* peak, uint8_t* gain,
                                                   float* q, float* t) {
   __shared__ uint32_t rows[EX == kExGlobal ? NT / kWave * 256 : 1];
+  __shared__ __attribute__((aligned(16))) uint16_t xrow[EX == kExNeighbour ? kNbrRows * (kMaxPix + 8) : 8];
   __shared__ int32_t start;
   const int64_t e = blockIdx.x;
   const int N = c.n_pix, np = c.n_pix_pad, T = c.n_samp;
   const uint16_t* ev = traces + e * c.event_elems;
   const size_t ob = (size_t)e * N;
   const __amdgpu_buffer_rsrc_t r = event_rsrc(ev, c.event_elems);
-  extract_event<EX, PPL, W, 2 * W, NT>(c, r, rows, &start, [&](int pix0, const uint32_t (&key)[PPL], uint32_t sw) {
+  extract_event<EX, PPL, W, 2 * W, NT>(c, r, ev, rows, &start, xrow, [&](int pix0, const uint32_t (&key)[PPL],
+                                                                         uint32_t sw) {
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
       const int i = pix0 + p;
@@ -1161,6 +1315,10 @@ hipError_t launch_calibrate_w(const DevCam& c, int ex, const uint16_t* tr, int64
       hipLaunchKernelGGL((k_calibrate<kExGlobal, kUnfusedPPL, W, kUnfusedNT>), dim3((unsigned)n), dim3(kUnfusedNT),
                          0, st, c, tr, S, D, ss, pk, g, q, t);
       break;
+    case kExNeighbour:
+      hipLaunchKernelGGL((k_calibrate<kExNeighbour, kUnfusedPPL, W, kUnfusedNT>), dim3((unsigned)n),
+                         dim3(kUnfusedNT), 0, st, c, tr, S, D, ss, pk, g, q, t);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1187,6 +1345,9 @@ hipError_t launch_fused_t(const FusedArgs& a, int grid, hipStream_t st) {
       break;
     case kExFixed: hipLaunchKernelGGL((k_fused_grid<kExFixed, PPL, W, CH, NT>), g1, dim3(NT), 0, st, a); break;
     case kExGlobal: hipLaunchKernelGGL((k_fused_grid<kExGlobal, PPL, W, CH, NT>), g1, dim3(NT), 0, st, a); break;
+    case kExNeighbour:
+      hipLaunchKernelGGL((k_fused_grid<kExNeighbour, PPL, W, CH, NT>), g1, dim3(NT), 0, st, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1216,7 +1377,9 @@ hipError_t launch_fused_w(const FusedArgs& a, const rta_schedule& s, int grid, h
 
 bool window_supported(int w) { return w == 4; }
 
-bool extractor_supported(int ex) { return ex == kExSliding || ex == kExFixed || ex == kExGlobal; }
+bool extractor_supported(int ex) {
+  return ex == kExSliding || ex == kExFixed || ex == kExGlobal || ex == kExNeighbour;
+}
 
 bool schedule_supported(const rta_schedule& s) {
   const bool ppl = s.pix_per_lane == 2 || s.pix_per_lane == 4 || s.pix_per_lane == 8;

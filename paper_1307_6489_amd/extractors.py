@@ -1,7 +1,7 @@
 """Signal extractors compared: charge resolution and throughput.
 
 The paper plans to port several signal-extraction algorithms to the GPU and
-measure them (Section 5).  This job compares the three extractors of the
+measure them (Section 5).  This job compares the four extractors of the
 library on the mixed dual-gain workload:
 
   resolution   generated events with their true Cherenkov photo-electron
@@ -26,7 +26,8 @@ import numpy as np
 
 import paper_1307_6489_amd as rta
 
-NAMES = {rta.EXTRACT_SLIDING: "sliding", rta.EXTRACT_FIXED: "fixed", rta.EXTRACT_GLOBAL_PEAK: "global_peak"}
+NAMES = {rta.EXTRACT_SLIDING: "sliding", rta.EXTRACT_FIXED: "fixed", rta.EXTRACT_GLOBAL_PEAK: "global_peak",
+         rta.EXTRACT_NEIGHBOUR_PEAK: "neighbour_peak"}
 NPE_BINS = (1, 3, 10, 30, 100, 300, 1000, 3000, 1e9)
 
 

@@ -1,5 +1,5 @@
 """GPU parity of the alternative signal extractors (fixed window, global peak
-window) against the oracle, through the C ABI: per-pixel integers bit-exact
+window, neighbour peak window) against the oracle, through the C ABI: per-pixel integers bit-exact
 (S, D, s*, peak, gain), q / t within FP32 rounding, Hillas records of the
 fused batch within the per-field tolerances of oracle/parity.py."""
 import numpy as np
@@ -12,8 +12,9 @@ import oracle.parity as par
 import paper_1307_6489_amd as rta
 
 pytestmark = pytest.mark.gpu
-EXS = [rta.EXTRACT_FIXED, rta.EXTRACT_GLOBAL_PEAK]
-NAME = {rta.EXTRACT_SLIDING: "sliding", rta.EXTRACT_FIXED: "fixed", rta.EXTRACT_GLOBAL_PEAK: "global peak"}
+EXS = [rta.EXTRACT_FIXED, rta.EXTRACT_GLOBAL_PEAK, rta.EXTRACT_NEIGHBOUR_PEAK]
+NAME = {rta.EXTRACT_SLIDING: "sliding", rta.EXTRACT_FIXED: "fixed", rta.EXTRACT_GLOBAL_PEAK: "global peak",
+        rta.EXTRACT_NEIGHBOUR_PEAK: "neighbour peak"}
 
 
 def say(*a):
@@ -205,7 +206,7 @@ def test_bad_extractor_is_rejected(torch_dev):
     cam = rta.Camera.from_type(ct)
     _, tr = dl0sim.plain_events(ct, 0, 1)
     with pytest.raises(rta.RTAError):
-        rta.calibrate(cam, to_dev(tr, torch_dev), extractor=3)
+        rta.calibrate(cam, to_dev(tr, torch_dev), extractor=4)
     with pytest.raises(rta.RTAError):
         rta.Pipeline([cam], do_stereo=False, extractor=-1)
     with pytest.raises(rta.RTAError):
