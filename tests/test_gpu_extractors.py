@@ -211,3 +211,57 @@ def test_bad_extractor_is_rejected(torch_dev):
         rta.Pipeline([cam], do_stereo=False, extractor=-1)
     with pytest.raises(rta.RTAError):
         rta.Camera.from_type(dl0sim.CameraType("bad", 1855, 30, 1, 28.0, fixed_start=27))
+
+
+@pytest.mark.parametrize("ex", [rta.EXTRACT_SLIDING] + EXS)
+def test_calibrate_small_cameras(torch_dev, ex):
+    """Cameras far below one workgroup's pixels (1, 7 and 61 pixels, padded
+    to 8 / 8 / 64 columns with garbage in the padding), the shortest traces
+    (T = w) and odd lengths, single and dual gain: every extractor against
+    the oracle (the lone pixel has no neighbours)."""
+    rng = np.random.default_rng(17)
+    for n, T, G in ((1, 4, 1), (7, 9, 2), (61, 33, 2), (61, 4, 1)):
+        ct = dl0sim.CameraType("tiny%d" % n, n, T, G, 5.0)
+        npad = (n + 7) // 8 * 8
+        tr = rng.integers(250, 4300, size=(5, G, T, npad), dtype=np.uint16)
+        say("small camera %d px x %d samples x %d gains, %s" % (n, T, G, NAME[ex]))
+        calib_parity(ct, tr, torch_dev, ex)
+
+
+@pytest.mark.parametrize("ex", [rta.EXTRACT_SLIDING] + EXS)
+def test_fused_small_cameras(torch_dev, ex):
+    """The fused batch on a mix of 1-, 7- and 61-pixel cameras (random dual-
+    and single-gain traces, switching included) in every extractor: records
+    against the oracle's whole chain."""
+    import torch
+    cams = [dl0sim.CameraType("tiny1", 1, 4, 1, 5.0), dl0sim.CameraType("tiny7", 7, 9, 2, 5.0),
+            dl0sim.CameraType("tiny61", 61, 33, 2, 5.0)]
+    rng = np.random.default_rng(23)
+    parts, ty, off, pos = [], [], [], 0
+    for k in range(24):
+        t = k % 3
+        c = cams[t]
+        ev = rng.integers(250, 4300, size=c.event_elems, dtype=np.uint16)
+        parts.append(ev)
+        ty.append(t)
+        off.append(pos)
+        pos += c.event_elems
+    blob = np.concatenate(parts)
+    say("fused small cameras, %s: 24 events" % NAME[ex])
+    pipe = rta.Pipeline([rta.Camera.from_type(c) for c in cams], do_stereo=False, extractor=ex)
+    b = pipe.make_batch(to_dev(blob, torch_dev), to_dev(np.array(ty, np.int32), torch_dev),
+                        to_dev(np.array(off, np.int64), torch_dev))
+    tel, _ = pipe.alloc_outputs(b, torch_dev)
+    pipe.process(b, tel)
+    torch.cuda.synchronize()
+    assert pipe.status() == 0
+    g = rta.records(tel)
+    ocs = [oracle.Camera.from_type(c, extractor=ex) for c in cams]
+    bad = []
+    for k in range(len(ty)):
+        c = cams[ty[k]]
+        p, m, h = ocs[ty[k]].reconstruct(blob[off[k]:off[k] + c.event_elems])
+        mm = par.hillas_mismatches(g[k], h, c.geom.x, c.geom.y, p["q"], p["t"], m)
+        if mm:
+            bad.append((k, mm))
+    assert not bad, bad[:3]
