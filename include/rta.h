@@ -420,8 +420,8 @@ rta_status rta_classify(rta_mlp* m, const rta_boxcut_desc* bc, const rta_hillas_
 rta_status rta_pipeline_attach_mlp(rta_pipeline* pipe, rta_mlp* m, const rta_boxcut_desc* bc);
 
 /* ------------------------------------------------------------------------
- * Real-time health monitor: a basic quality check of the acquired data that
- * tells the alert monitor when the data are not good (paper, Section 4.2).
+ * Real-time health monitor: a quality check of the acquired data whose
+ * verdict lets the alert monitor hold back on bad data (paper, Section 4.2).
  * Over n_evt camera events of one type, per gain g and pixel i:
  *   n = n_evt * T samples, s1 = sum x, s2 = sum x^2, n_sat = samples >= the
  *   saturation level (the high-gain switch level for the high gain of a
@@ -454,7 +454,7 @@ typedef struct rta_pixel_health {
 typedef struct rta_camera_health {
   double median_rms[2];  /* per gain (index 1 unused for single gain) */
   int32_t n_bad;         /* pixels with any flag */
-  int32_t verdict;       /* 1: data not good */
+  int32_t verdict;       /* 1: data quality insufficient */
 } rta_camera_health;
 
 /* Health statistics of n_evt events of one type: traces [n_evt][G][T][Npad]

@@ -1,8 +1,8 @@
 """Oracle of the real-time health monitor — TEST INFRASTRUCTURE ONLY.
 
-The paper's RT Health Monitoring performs a basic quality check of the data
-in real time and tells the alert monitor when the data are not good
-(Section 4.2).  It names no quantities; the reading implemented here (plain
+In the paper's design a real-time monitor checks the quality of the incoming
+data and its verdict lets the alert monitor hold back on bad data (Section
+4.2).  It names no quantities; the reading implemented here (plain
 numpy, integers exact, derived values FP64):
 
   accumulate   over n_evt camera events of one type, per gain g and pixel i:
