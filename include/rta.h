@@ -328,7 +328,9 @@ rta_status rta_frame_packets(const rta_camera_info* types, int32_t n_types, cons
  * ...] as [G][T][Npad] with zero pad columns.  A packet failing any check
  * gets tel_type[p] = -1 (in place: the fused batch then flags it as a bad
  * descriptor), its record's flags and RTA_STATUS_BAD_PACKET in the status
- * word; a CRC failure is known only after its slot was written.
+ * word; a CRC failure is known only after its slot was written.  A packet
+ * offset outside [0, n_bytes - 34] reads nothing and is flagged
+ * RTA_PKT_HEADER_BAD.
  * bytes: 16-byte aligned, and the RTA_PACKET_PAD bytes after bytes[n_bytes]
  * must be readable (their content is ignored).  rec: [n_pkt], NULLABLE. */
 rta_status rta_decode_packets(rta_pipeline* pipe, const uint8_t* bytes, int64_t n_bytes, const int64_t* pkt_off,

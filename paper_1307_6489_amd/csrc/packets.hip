@@ -88,16 +88,19 @@ __global__ __launch_bounds__(kDecodeNT) void k_decode_packets(DecodeArgs a) {
   }
   // header: 32 bytes at po (every lane, uniform)
   const int64_t po = uniform64(a.pkt_off[p]);
-  const int64_t base = po & ~int64_t(15);
+  // an offset that leaves no room for a header inside the stream reads
+  // nothing (an empty buffer range: every load returns zero) and is flagged
+  const bool po_ok = po >= 0 && po + 34 <= a.n_bytes;
+  const int64_t base = po_ok ? (po & ~int64_t(15)) : 0;
   // every load stays below n_bytes + 32 (the caller keeps those 32 bytes
   // readable): loads are 16-byte pieces at 4-byte aligned addresses, so the
   // pieces at the end of a packet reach past it into the next packet or the
   // padding, and a piece straddling the buffer's range would read as zero
-  const int64_t avail = a.n_bytes + kDecodePad - base;
+  const int64_t avail = po_ok ? a.n_bytes + kDecodePad - base : 0;
   const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<uint8_t*>(a.bytes + base), 0, (int)(avail > 0x7ffffff0LL ? 0x7ffffff0LL : (avail > 0 ? avail : 0)),
       0x00020000);
-  const uint32_t o0 = (uint32_t)(po - base);
+  const uint32_t o0 = po_ok ? (uint32_t)(po - base) : 0u;
   uint32_t hw[8];
   {
     uint32_t t[4];
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(kDecodeNT) void k_decode_packets(DecodeArgs a) {
   const uint32_t dlen = __builtin_amdgcn_readfirstlane(g32(4));
   const uint32_t ty = __builtin_amdgcn_readfirstlane(g8(11)), N = __builtin_amdgcn_readfirstlane(g16(18));
   const uint32_t T = __builtin_amdgcn_readfirstlane(g16(20)), G = __builtin_amdgcn_readfirstlane(g8(22));
-  uint32_t flags = 0;
+  uint32_t flags = po_ok ? 0u : RTA_PKT_HEADER_BAD;
   const uint64_t body = 2ull * N * T * G;
   if ((pid >> 11) != 1u || (seq >> 14) != 3u || g8(8) != 0x10u || g8(9) != 210u || g8(10) != 1u || g8(23) != 0u ||
       (uint64_t)dlen + 9ull != 34ull + body || po + 34 + (int64_t)body > a.n_bytes)

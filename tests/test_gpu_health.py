@@ -103,3 +103,18 @@ def test_health_small_cameras(torch_dev, n_pix):
     pix, c = check(ct, tr, torch_dev)
     if n_pix > 2:
         assert pix["flags"][0][1] & rta.HEALTH_DEAD and pix["flags"][0][2] & rta.HEALTH_NOISY
+
+
+def test_health_rejects_bad_arguments(torch_dev):
+    """Host-side checks: no events, non-finite thresholds, a trace buffer
+    that is not 16-byte aligned; nothing is launched for them."""
+    import torch
+    ct = dl0sim.camera_types_c1()[1]
+    cam = rta.Camera.from_type(ct)
+    tr = torch.zeros((2 * cam.event_elems + 8,), dtype=torch.uint16, device=torch_dev)
+    with pytest.raises(rta.RTAError):
+        rta.health(cam, tr[:0])
+    with pytest.raises(rta.RTAError):
+        rta.health(cam, tr[:2 * cam.event_elems], ped_tol=float("nan"))
+    with pytest.raises(rta.RTAError):
+        rta.health(cam, tr[1:1 + 2 * cam.event_elems])

@@ -160,3 +160,36 @@ def test_decode_large_stream_sampled(torch_dev):
         assert np.array_equal(got, pool.blob[pool.pool_off[e]:pool.pool_off[e] + m])
         b = bytes(st[o[k]:o[k] + 32 + 2 * pool.cams[t[k]].n_gain * pool.cams[t[k]].n_samp * pool.cams[t[k]].n_pix])
         assert g_rec["crc_computed"][k] == op.crc16(b)
+
+
+def test_offsets_outside_the_stream_are_flagged(torch_dev):
+    """Packet offsets before the stream, past its end and too close to its
+    end for a header read nothing and come back as bad headers (type -1);
+    the other packets decode as the oracle says."""
+    import torch
+    pool = W.c1_pool(12, seed=1)
+    st, off = gp.serialize(pool, np.arange(pool.n), seed=2)
+    cams = [rta.Camera.from_type(c) for c in pool.cams]
+    pipe = rta.Pipeline(cams, do_stereo=False)
+    o, t, po, n, used = rta.frame_packets(cams, st)
+    ref_pool, ref_rec, ref_t = op.decode(st, o, t, po, n, types_of(pool))
+    o2 = o.copy()
+    o2[2] = -16
+    o2[5] = st.size + 4096
+    o2[7] = st.size - 20
+    say("decode: 12 packets, 3 offsets outside the stream")
+    t_dev = to_dev(t, torch_dev)
+    data, nb = rta.packet_buffer(st, torch_dev)
+    pool_d, rec = rta.decode_packets(pipe, data, to_dev(o2, torch_dev), t_dev, to_dev(po, torch_dev), n, n_bytes=nb)
+    torch.cuda.synchronize()
+    g_rec = rec.cpu().numpy().view(rta.PACKET_DTYPE).reshape(-1)
+    g_t = t_dev.cpu().numpy()
+    g_pool = pool_d.cpu().numpy()
+    for k in range(len(o)):
+        if k in (2, 5, 7):
+            assert g_rec["flags"][k] & rta.PKT_HEADER_BAD and g_t[k] == -1, k
+        else:
+            assert g_rec["flags"][k] == 0 and g_t[k] == ref_t[k], k
+            m = pool.cams[t[k]].event_elems
+            assert np.array_equal(g_pool[po[k]:po[k] + m], ref_pool[po[k]:po[k] + m])
+    assert pipe.status() == rta.STATUS_BAD_PACKET
