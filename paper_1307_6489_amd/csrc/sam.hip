@@ -102,19 +102,22 @@ __global__ void k_sam_search(SamDev d, double* __restrict__ sig, int32_t* __rest
   const int cell = (int)(i - s * G2);
   const int y = cell / G, x = cell - y * G;
   const int32_t* W = d.win + s * G2;
+  // branch-free body (cells outside the grid read a clamped cell and add
+  // nothing), unrolled so that several window-sum loads are in flight
   int64_t n_on = 0, n_off = 0, c_on = 0, c_off = 0;
+#pragma unroll 8
   for (int k = 0; k < d.n_offs; ++k) {
     const int32_t o = d.offs[k];
     const int xx = x + (o & 0xFF) - 128, yy = y + ((o >> 8) & 0xFF) - 128;
-    if (xx < 0 || xx >= G || yy < 0 || yy >= G) continue;
-    const int32_t v = W[(int64_t)yy * G + xx];
-    if ((o >> 16) == 1) {
-      n_on += v;
-      ++c_on;
-    } else {
-      n_off += v;
-      ++c_off;
-    }
+    const bool in = xx >= 0 && xx < G && yy >= 0 && yy < G;
+    const int32_t v = W[(int64_t)min(max(yy, 0), G - 1) * G + min(max(xx, 0), G - 1)];
+    const int64_t vi = in ? (int64_t)v : 0;
+    const int64_t ci = in ? 1 : 0;
+    const bool on = (o >> 16) == 1;
+    n_on += on ? vi : 0;
+    c_on += on ? ci : 0;
+    n_off += on ? 0 : vi;
+    c_off += on ? 0 : ci;
   }
   const double S = li_ma(n_on, n_off, c_on, c_off);
   if (sig) sig[i] = S;
