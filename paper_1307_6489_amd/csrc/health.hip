@@ -12,10 +12,10 @@
 //   reduce      per pixel and quantity, the sum of the partial blocks (16
 //               slices of blocks per output, combined in LDS), so the totals
 //               are exact integers independent of the schedule;
-//   evaluate    one workgroup: FP64 mean / rms without contraction, a
-//               bitonic sort of the rms (registers, lane shuffles and LDS)
-//               for the lower median, flags, the bad-pixel count and the
-//               verdict.
+//   evaluate    one workgroup per gain: FP64 mean / rms without
+//               contraction, a bitonic sort of the rms (registers, lane
+//               shuffles and LDS) for the lower median, the flags;
+//   verdict     one workgroup: pixels flagged in any gain, the verdict.
 #include <cmath>
 
 #include "rta_internal.h"
@@ -158,127 +158,115 @@ __device__ __forceinline__ double bitonic_step(double v, double p, int i, int j,
   return take_min ? fmin(v, p) : fmax(v, p);
 }
 
-// Evaluation: thread t owns pixels t and t + 1024 of both gains.  The rms of
-// each gain, padded with +inf to 2048 values, is sorted ascending by a
+// Evaluation, one workgroup per gain: thread t owns pixels t and t + 1024.
+// The gain's rms, padded with +inf to 2048 values, is sorted ascending by a
 // bitonic network on registers: partners within a wavefront (j < 64) by
-// lane shuffles, across wavefronts through LDS, j = 1024 inside the
-// thread; both gains go through the network together.
+// lane shuffles, across wavefronts through LDS, j = 1024 inside the thread.
 static_assert(2 * kEvalNT == kMaxPix, "two pixels per evaluation thread");
 
 __global__ __launch_bounds__(kEvalNT) void k_health_eval(DevCam c, const uint64_t* __restrict__ acc, int64_t n_evt,
                                                          rta_health_params prm, rta_pixel_health* __restrict__ pix,
                                                          rta_camera_health* __restrict__ out) {
-  __shared__ double xch[2][kMaxPix];
-  __shared__ double s_med[2];
-  __shared__ int32_t nbad;
+  __shared__ double xch[kMaxPix];
+  __shared__ double s_med;
   const int N = c.n_pix, np = c.n_pix_pad, G = c.n_gain;
-  const int t = threadIdx.x;
+  const int g = blockIdx.x, t = threadIdx.x;
   const uint64_t n = (uint64_t)n_evt * (uint64_t)c.n_samp;
   const int64_t plane = (int64_t)G * np;
-  if (t == 0) nbad = 0;
-  uint64_t a1[2][2], a2[2][2], a3[2][2];
-  double mean[2][2], rms[2][2], v[2][2];
+  uint64_t a1[2], a2[2], a3[2];
+  double mean[2], rms[2], v[2];
 #pragma unroll
-  for (int g = 0; g < 2; ++g)
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int i = t + kEvalNT * e;
-      a1[g][e] = a2[g][e] = a3[g][e] = 0;
-      mean[g][e] = rms[g][e] = 0.0;
-      v[g][e] = INFINITY;
-      if (g < G && i < N) {
-        const int64_t o = (int64_t)g * np + i;
-        a1[g][e] = acc[o];
-        a2[g][e] = acc[plane + o];
-        a3[g][e] = acc[2 * plane + o];
-        pixel_stats(a1[g][e], a2[g][e], n, mean[g][e], rms[g][e]);
-        v[g][e] = rms[g][e];
-      }
+  for (int e = 0; e < 2; ++e) {
+    const int i = t + kEvalNT * e;
+    a1[e] = a2[e] = a3[e] = 0;
+    mean[e] = rms[e] = 0.0;
+    v[e] = INFINITY;
+    if (i < N) {
+      const int64_t o = (int64_t)g * np + i;
+      a1[e] = acc[o];
+      a2[e] = acc[plane + o];
+      a3[e] = acc[2 * plane + o];
+      pixel_stats(a1[e], a2[e], n, mean[e], rms[e]);
+      v[e] = rms[e];
     }
+  }
 #pragma unroll
   for (int k = 2; k <= kMaxPix; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      double p[2][2];
+      double p[2];
       if (j == kEvalNT) {
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-          p[g][0] = v[g][1];
-          p[g][1] = v[g][0];
-        }
+        p[0] = v[1];
+        p[1] = v[0];
       } else if (j >= kWave) {
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-          xch[g][t] = v[g][0];
-          xch[g][t + kEvalNT] = v[g][1];
-        }
+        xch[t] = v[0];
+        xch[t + kEvalNT] = v[1];
         __syncthreads();
 #pragma unroll
-        for (int g = 0; g < 2; ++g)
-#pragma unroll
-          for (int e = 0; e < 2; ++e) p[g][e] = xch[g][(t + kEvalNT * e) ^ j];
+        for (int e = 0; e < 2; ++e) p[e] = xch[(t + kEvalNT * e) ^ j];
         __syncthreads();
       } else {
 #pragma unroll
-        for (int g = 0; g < 2; ++g)
-#pragma unroll
-          for (int e = 0; e < 2; ++e) p[g][e] = __shfl_xor(v[g][e], j, kWave);
+        for (int e = 0; e < 2; ++e) p[e] = __shfl_xor(v[e], j, kWave);
       }
 #pragma unroll
-      for (int g = 0; g < 2; ++g)
-#pragma unroll
-        for (int e = 0; e < 2; ++e) v[g][e] = bitonic_step(v[g][e], p[g][e], t + kEvalNT * e, j, k);
+      for (int e = 0; e < 2; ++e) v[e] = bitonic_step(v[e], p[e], t + kEvalNT * e, j, k);
     }
   }
-  // lower median: sorted element (N - 1) / 2 of each gain
+  // lower median: sorted element (N - 1) / 2
   const int mi = (N - 1) / 2;
 #pragma unroll
   for (int e = 0; e < 2; ++e)
     if (t + kEvalNT * e == mi) {
-      s_med[0] = v[0][e];
-      s_med[1] = v[1][e];
+      s_med = v[e];
+      out->median_rms[g] = v[e];
     }
   __syncthreads();
-  const double med[2] = {s_med[0], s_med[1]};
-  int mine = 0;
+  const double med = s_med;
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const int i = t + kEvalNT * e;
     if (i >= N) continue;
-    uint32_t any = 0;
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      if (g >= G) break;
-      uint32_t f = 0;
-      if (rms[g][e] < (double)prm.rms_dead) f |= RTA_HEALTH_DEAD;
-      if (rms[g][e] > (double)prm.noisy_factor * med[g]) f |= RTA_HEALTH_NOISY;
-      const double ped = (double)c.P256[g * np + i] / 256.0;
-      if (fabs(mean[g][e] - ped) > (double)prm.ped_tol) f |= RTA_HEALTH_PED_SHIFT;
-      if ((double)a3[g][e] > (double)prm.sat_frac * (double)n) f |= RTA_HEALTH_SATURATING;
-      rta_pixel_health h;
-      h.n = n;
-      h.s1 = a1[g][e];
-      h.s2 = a2[g][e];
-      h.n_sat = a3[g][e];
-      h.mean = mean[g][e];
-      h.rms = rms[g][e];
-      h.flags = f;
-      h.pad_ = 0;
-      h.reserved_ = 0;
-      pix[(int64_t)g * N + i] = h;
-      any |= f;
-    }
+    uint32_t f = 0;
+    if (rms[e] < (double)prm.rms_dead) f |= RTA_HEALTH_DEAD;
+    if (rms[e] > (double)prm.noisy_factor * med) f |= RTA_HEALTH_NOISY;
+    const double ped = (double)c.P256[g * np + i] / 256.0;
+    if (fabs(mean[e] - ped) > (double)prm.ped_tol) f |= RTA_HEALTH_PED_SHIFT;
+    if ((double)a3[e] > (double)prm.sat_frac * (double)n) f |= RTA_HEALTH_SATURATING;
+    rta_pixel_health h;
+    h.n = n;
+    h.s1 = a1[e];
+    h.s2 = a2[e];
+    h.n_sat = a3[e];
+    h.mean = mean[e];
+    h.rms = rms[e];
+    h.flags = f;
+    h.pad_ = 0;
+    h.reserved_ = 0;
+    pix[(int64_t)g * N + i] = h;
+  }
+}
+
+// Verdict: pixels with a flag in any gain, from the records just written.
+__global__ __launch_bounds__(kEvalNT) void k_health_verdict(DevCam c, rta_health_params prm,
+                                                            const rta_pixel_health* __restrict__ pix,
+                                                            rta_camera_health* __restrict__ out) {
+  __shared__ int32_t nbad;
+  const int N = c.n_pix, G = c.n_gain;
+  if (threadIdx.x == 0) nbad = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int i = threadIdx.x; i < N; i += kEvalNT) {
+    uint32_t any = pix[i].flags;
+    if (G == 2) any |= pix[(int64_t)N + i].flags;
     mine += any ? 1 : 0;
   }
   if (mine) atomicAdd(&nbad, mine);
   __syncthreads();
-  if (t == 0) {
-    rta_camera_health r;
-    r.median_rms[0] = med[0];
-    r.median_rms[1] = G == 2 ? med[1] : 0.0;
-    r.n_bad = nbad;
-    r.verdict = (double)nbad > (double)prm.bad_frac_max * (double)N ? 1 : 0;
-    *out = r;
+  if (threadIdx.x == 0) {
+    if (G == 1) out->median_rms[1] = 0.0;
+    out->n_bad = nbad;
+    out->verdict = (double)nbad > (double)prm.bad_frac_max * (double)N ? 1 : 0;
   }
 }
 
@@ -294,7 +282,9 @@ hipError_t launch_health(const DevCam& c, const uint16_t* traces, int64_t n_evt,
   hipLaunchKernelGGL(k_health_accum, dim3((unsigned)grid), dim3(kHealthNT), 0, st, c, traces, n_evt, part);
   hipLaunchKernelGGL(k_health_reduce, dim3((unsigned)((n_out + kRedOut - 1) / kRedOut)), dim3(kRedOut * kRedSlices),
                      0, st, (const uint64_t*)part, n_out, grid, acc);
-  hipLaunchKernelGGL(k_health_eval, dim3(1), dim3(kEvalNT), 0, st, c, (const uint64_t*)acc, n_evt, p, pix, out);
+  hipLaunchKernelGGL(k_health_eval, dim3((unsigned)c.n_gain), dim3(kEvalNT), 0, st, c, (const uint64_t*)acc, n_evt, p,
+                     pix, out);
+  hipLaunchKernelGGL(k_health_verdict, dim3(1), dim3(kEvalNT), 0, st, c, p, (const rta_pixel_health*)pix, out);
   return hipGetLastError();
 }
 
