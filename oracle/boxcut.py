@@ -6,6 +6,9 @@ decides when all ten features are finite and inside the trained range,
 otherwise the scaled-width / scaled-length box cut decides and the energy is
 the linear fit in log10 size.  Decisions that are integers are taken in
 float32, the precision of the kernels.
+
+Parity status: pinned by hand-derived decisions, bin clamping and fallback
+cases (tests/test_oracle_boxcut.py).
 """
 from __future__ import annotations
 

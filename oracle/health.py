@@ -18,6 +18,9 @@ numpy, integers exact, derived values FP64):
                (256 ped), the Q8 pedestal the calibration uses, ADC);
                SATURATING n_sat > sat_frac * n
   verdict      bad pixels (any flag, any gain) > bad_frac_max * N  ->  1
+
+Parity status: pinned by a direct loop, hand-made bad pixels, the lower
+median and the generator's noise (tests/test_oracle_health.py).
 """
 from __future__ import annotations
 

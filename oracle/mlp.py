@@ -22,6 +22,9 @@ Mixed precision, as the kernels do it (bfloat16 storage, wide accumulation):
 
 bfloat16 rounding is round-to-nearest-even of the float32 value.  Sums here
 are FP64; the kernels accumulate in FP32, so parity is to a tolerance.
+
+Parity status: pinned by bf16 known values, a closed-form forward pass, loss
+values, finite differences and the first Adam step (tests/test_oracle_mlp.py).
 """
 from __future__ import annotations
 

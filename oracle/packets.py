@@ -28,6 +28,10 @@ samples become little-endian uint16 [G][T][Npad] with zero pad columns.
 
 Plain loops and numpy; the CRC is the bitwise C routine oracle_crc16.  Shares
 no code with the HIP library.
+
+Parity status: pinned by the CRC's check value, residue and error detection,
+a hand-assembled packet and the generator's stream (tests/test_oracle_packets.py,
+tests/test_packets_host.py).
 """
 from __future__ import annotations
 

@@ -27,6 +27,10 @@ the reading implemented here (plain loops and numpy, FP64):
                excess is exactly zero (N_on * off cells == on cells * N_off,
                decided in integers)
   alert        S >= sigma_alert
+
+Parity status: pinned by the Poisson likelihood ratio, closed special cases,
+numpy.histogramdd, a flat sky, mirror symmetry and a planted flare
+(tests/test_oracle_sam.py).
 """
 from __future__ import annotations
 
