@@ -118,3 +118,30 @@ def test_health_rejects_bad_arguments(torch_dev):
         rta.health(cam, tr[:2 * cam.event_elems], ped_tol=float("nan"))
     with pytest.raises(rta.RTAError):
         rta.health(cam, tr[1:1 + 2 * cam.event_elems])
+
+
+def test_health_full_size_sampled(torch_dev):
+    """The measured job: 2000 signal-free 2048 x 128 dual-gain events (2.1
+    GB, 200 generated events tiled ten times).  64 sampled pixels against
+    the oracle on their columns: counts, sums, mean and rms exact, the flags
+    that do not involve the camera median exact; the median is the lower
+    median of the returned rms values."""
+    import torch
+    ct = dl0sim.camera_types_c1()[2]
+    sh = dl0sim.draw_ellipses(dl0sim.draw_cfg_plain(ct.n_samp), 21, 0, 200)
+    sh["size"][:, 0] = 0.0
+    base = dl0sim.render_traces(ct, sh, 21)
+    tr = np.tile(base, (10, 1, 1, 1))
+    say("health, full size: 2000 x 2048 x 128 x 2")
+    cam = rta.Camera.from_type(ct)
+    pix, c = rta.health(cam, torch.from_numpy(np.ascontiguousarray(tr)).to(torch_dev), **P)
+    idx = np.sort(np.random.default_rng(5).choice(ct.n_pix, 64, replace=False))
+    rp, rc = oh.health(np.ascontiguousarray(tr[..., idx]), 64, ct.n_gain, ct.ped[:, idx], ct.hg_switch_adc, P)
+    assert np.array_equal(pix["n"][:, idx].astype(np.int64), rp["n"])
+    for k in ("S1", "S2", "n_sat"):
+        assert np.array_equal(pix[k.lower()][:, idx].astype(np.int64), rp[k]), k
+    assert np.array_equal(pix["mean"][:, idx], rp["mean"]) and np.array_equal(pix["rms"][:, idx], rp["rms"])
+    keep = rta.HEALTH_DEAD | rta.HEALTH_PED_SHIFT | rta.HEALTH_SATURATING
+    assert np.array_equal(pix["flags"][:, idx].astype(np.int64) & keep, rp["flags"] & keep)
+    for g in range(ct.n_gain):
+        assert c["median_rms"][g] == np.sort(pix["rms"][g])[(ct.n_pix - 1) // 2]

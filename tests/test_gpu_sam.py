@@ -126,3 +126,36 @@ def test_bad_parameters_rejected(torch_dev):
                 dict(P, scales=[P["n_bins"] + 1])):
         with pytest.raises(rta.RTAError):
             make_sam(bad)
+
+
+def test_full_size_hour_sampled(torch_dev):
+    """The measured monitor job: a 1-hour 3 kHz event list (10.8 M events)
+    into 64 x 64 cells of 1.5 mrad x 3600 one-second bins, windows of 1 s to
+    1 h.  Six sampled time bins of the counts cube against the oracle's
+    histogram of the events around them (exact), and the search at the last
+    bin against the oracle's search of the same cube: N_on, N_off exact, S to
+    rounding, alerts exact."""
+    p = {"grid": 64, "cell": 0.0015, "t0": 0.0, "bin_s": 1.0, "n_bins": 3600, "r_on": 1.5, "r_in": 3.5,
+         "r_out": 7.0, "gamma_cut": 0.7, "scales": [1, 10, 60, 600, 3600], "sigma_alert": 5.0}
+    t, d, g, v = W.sam_events(11, 3600.0, 3000.0, 0.05, [])
+    say("alert monitor, full size: %d events" % len(t))
+    sam = make_sam(p)
+    e, td = to_dev(records(d, g, v), t, torch_dev)
+    sam.fill(e, td)
+    C = sam.counts().astype(np.int64)
+    rng = np.random.default_rng(31)
+    for b in [0, 1799, 3599] + [int(x) for x in rng.integers(1, 3599, 3)]:
+        m = (t >= b - 1.0) & (t < b + 2.0)
+        Cb, _ = osam.histogram(d[m], t[m], g[m], v[m], p)
+        assert np.array_equal(C[b], Cb[b]), b
+    say("alert monitor, full size: search at bin 3599")
+    ref, ref_alerts = osam.search(C, 3599, p)
+    sig, non, noff, alerts, n_found = sam.search(3599)
+    sig, non, noff = sig.cpu().numpy(), non.cpu().numpy(), noff.cpu().numpy()
+    for si, r in enumerate(ref):
+        assert np.array_equal(non[si].astype(np.int64), r["N_on"])
+        assert np.array_equal(noff[si].astype(np.int64), r["N_off"])
+        assert np.allclose(sig[si], r["S"], rtol=1e-12, atol=1e-12)
+    near = {(si, x, y) for si, x, y, s in ref_alerts if abs(s - p["sigma_alert"]) < 1e-9}
+    got = {(int(a["scale"]), int(a["ix"]), int(a["iy"])) for a in alerts} - near
+    assert got == {(si, x, y) for si, x, y, s in ref_alerts} - near and n_found == len(alerts)
