@@ -462,15 +462,19 @@ __device__ __forceinline__ int global_start(const uint32_t* rows, int T, int32_t
 // stands in for a missing neighbour), so a pixel's neighbours cost one 8-byte
 // read each per four slices, and the per-slice neighbour sums y(t) come from
 // packed dot products.  The next four slices are loaded while the current
-// ones are used.  Each lane keeps, for each of its pixels, the last
+// ones are used.  In this stage lane t takes pixels t, t + NT, ... (so the
+// lanes of one read touch consecutive words); the pixels' best keys then go
+// through LDS to the lanes' PPL-pixel groups.  Each lane keeps, for each of its pixels, the last
 // W-1 sums to form C(t-W+1), the best key (C << 8) | (255 - s) and the raw
 // high-gain maximum (gain decision on the whole trace, as for the sliding
 // window).  Then the pixel's own W samples at its start on its selected gain
 // give S.  Called by every thread of the block (contains barriers).
 template <int PPL, int W, int NT, class Fn>
 __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer_rsrc_t r,
-                                                const uint16_t* __restrict__ ev, uint16_t* xrow, Fn&& fn) {
+                                                const uint16_t* __restrict__ ev, uint16_t* xrow, uint32_t* keys,
+                                                Fn&& fn) {
   static_assert(kNbrRows == 4, "four slices per staged pixel word pair");
+  constexpr int MAXK = (kMaxPix + NT - 1) / NT;  // pixels per lane: t, t + NT, ...
   constexpr int MAXP = (kMaxPix + NT * PPL - 1) / (NT * PPL);
   const int N = c.n_pix, np = c.n_pix_pad, T = c.n_samp;
   const bool dual = c.n_gain == 2;
@@ -479,35 +483,32 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
   // one (64-bit words: the packed dot of a two-lane vector's second element
   // has been seen compiled onto its first)
   uint64_t* xs = reinterpret_cast<uint64_t*>(xrow);
-  // pixel j = 8 g + m of 16-byte group g lives in word m * (Npad / 8) + g,
-  // so the eight words a stager writes land in eight rows of consecutive
-  // words (no bank conflicts between the lanes of a store)
-  const uint32_t g8 = (uint32_t)np / 8u;
-  auto slot = [g8](uint32_t j) { return (j & 7u) * g8 + (j >> 3); };
-  uint32_t nb[MAXP][PPL][3];      // six neighbour indices per pixel, packed int16 (Npad if missing)
-  uint32_t ring[MAXP][PPL][W - 1];
-  uint32_t best[MAXP][PPL], hmax[MAXP][PPL];
+  // pixel j = 8 g + m of 16-byte group g lives in word 8 g + (m ^ (g & 7)):
+  // consecutive lanes reading consecutive pixels, and the lanes of one
+  // staging store, each touch distinct banks
+  auto slot = [](uint32_t j) { return (j & ~7u) | ((j ^ (j >> 3)) & 7u); };
+  uint32_t nb[MAXK][3];  // six neighbour words per pixel, packed 16-bit slots (Npad if missing)
+  uint32_t ring[MAXK][W - 1];
+  uint32_t best[MAXK], hmax[MAXK];
 #pragma unroll
-  for (int ps = 0; ps < MAXP; ++ps)
+  for (int k = 0; k < MAXK; ++k) {
+    const int i = (int)threadIdx.x + k * NT;
+    nb[k][0] = nb[k][1] = nb[k][2] = (uint32_t)np * 0x10001u;
+    if (i < N) {
+      const int4 v = *reinterpret_cast<const int4*>(c.nbr + (size_t)i * kNbrCols);
+      const uint32_t w3[3] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z};
 #pragma unroll
-    for (int p = 0; p < PPL; ++p) {
-      const int i = (ps * NT + (int)threadIdx.x) * PPL + p;
-      nb[ps][p][0] = nb[ps][p][1] = nb[ps][p][2] = (uint32_t)np * 0x10001u;
-      if (ps < npass && i < N) {
-        const int4 v = *reinterpret_cast<const int4*>(c.nbr + (size_t)i * kNbrCols);
-        const uint32_t w3[3] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z};
-#pragma unroll
-        for (int h = 0; h < 3; ++h) {
-          const uint32_t lo = (w3[h] & 0x8000u) ? (uint32_t)np : slot(w3[h] & 0xffffu);
-          const uint32_t hi = (w3[h] & 0x80000000u) ? (uint32_t)np : slot(w3[h] >> 16);
-          nb[ps][p][h] = lo | (hi << 16);
-        }
+      for (int h = 0; h < 3; ++h) {
+        const uint32_t lo = (w3[h] & 0x8000u) ? (uint32_t)np : slot(w3[h] & 0xffffu);
+        const uint32_t hi = (w3[h] & 0x80000000u) ? (uint32_t)np : slot(w3[h] >> 16);
+        nb[k][h] = lo | (hi << 16);
       }
-#pragma unroll
-      for (int k = 0; k < W - 1; ++k) ring[ps][p][k] = 0;
-      best[ps][p] = 0;
-      hmax[ps][p] = 0;
     }
+#pragma unroll
+    for (int u = 0; u < W - 1; ++u) ring[k][u] = 0;
+    best[k] = 0;
+    hmax[k] = 0;
+  }
   if (threadIdx.x == 0) xs[np] = 0ull;
   // thread q stages 16-byte pixel group q (np / 8 <= kMaxPix / 8 <= NT
   // groups), the next four slices loaded while the current ones are used
@@ -528,47 +529,53 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const uint32_t sel = (m & 1) ? 0x07060302u : 0x05040100u;  // high / low halfwords
-        xs[m * g8 + q] = (uint64_t)__builtin_amdgcn_perm(d[1][m >> 1], d[0][m >> 1], sel) |
-                        ((uint64_t)__builtin_amdgcn_perm(d[3][m >> 1], d[2][m >> 1], sel) << 32);
+        xs[q * 8 + (m ^ (q & 7))] = (uint64_t)__builtin_amdgcn_perm(d[1][m >> 1], d[0][m >> 1], sel) |
+                                    ((uint64_t)__builtin_amdgcn_perm(d[3][m >> 1], d[2][m >> 1], sel) << 32);
       }
     }
     __syncthreads();
     if (stager && k0 + kNbrRows < T) load4(k0 + kNbrRows);
 #pragma unroll
-    for (int ps = 0; ps < MAXP; ++ps)
+    for (int k = 0; k < MAXK; ++k) {
+      const int i = (int)threadIdx.x + k * NT;
+      if (i >= N) continue;
+      uint32_t y[kNbrRows] = {0u, 0u, 0u, 0u};
 #pragma unroll
-      for (int p = 0; p < PPL; ++p) {
-        const int i = (ps * NT + (int)threadIdx.x) * PPL + p;
-        if (ps >= npass || i >= N) continue;
-        uint32_t y[kNbrRows] = {0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-          const int jn = (int)((nb[ps][p][m >> 1] >> ((m & 1) * 16)) & 0xffffu);
-          const uint64_t v = xs[jn];
-          const uint32_t v01 = (uint32_t)v, v23 = (uint32_t)(v >> 32);
-          y[0] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v01), row_lo, y[0], false);
-          y[1] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v01), row_hi, y[1], false);
-          y[2] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v23), row_lo, y[2], false);
-          y[3] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v23), row_hi, y[3], false);
-        }
-        const uint64_t own = xs[slot((uint32_t)i)];
-        const uint32_t o01 = (uint32_t)own, o23 = (uint32_t)(own >> 32);
-        const uint32_t xo[kNbrRows] = {lo16(o01), hi16(o01), lo16(o23), hi16(o23)};
-#pragma unroll
-        for (int k = 0; k < kNbrRows; ++k) {
-          const int t = k0 + k;
-          if (t >= T) break;
-          hmax[ps][p] = max(hmax[ps][p], xo[k]);
-          uint32_t C = y[k];
-#pragma unroll
-          for (int u = 0; u < W - 1; ++u) C += ring[ps][p][u];
-          if (t >= W - 1) best[ps][p] = max(best[ps][p], (C << 8) | (uint32_t)(255 - (t - (W - 1))));
-#pragma unroll
-          for (int u = W - 2; u > 0; --u) ring[ps][p][u] = ring[ps][p][u - 1];
-          ring[ps][p][0] = y[k];
-        }
+      for (int m = 0; m < 6; ++m) {
+        const int jn = (int)((nb[k][m >> 1] >> ((m & 1) * 16)) & 0xffffu);
+        const uint64_t v = xs[jn];
+        const uint32_t v01 = (uint32_t)v, v23 = (uint32_t)(v >> 32);
+        y[0] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v01), row_lo, y[0], false);
+        y[1] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v01), row_hi, y[1], false);
+        y[2] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v23), row_lo, y[2], false);
+        y[3] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v23), row_hi, y[3], false);
       }
+      const uint64_t own = xs[slot((uint32_t)i)];
+      const uint32_t o01 = (uint32_t)own, o23 = (uint32_t)(own >> 32);
+      const uint32_t xo[kNbrRows] = {lo16(o01), hi16(o01), lo16(o23), hi16(o23)};
+#pragma unroll
+      for (int u = 0; u < kNbrRows; ++u) {
+        const int t = k0 + u;
+        if (t >= T) break;
+        hmax[k] = max(hmax[k], xo[u]);
+        uint32_t C = y[u];
+#pragma unroll
+        for (int z = 0; z < W - 1; ++z) C += ring[k][z];
+        if (t >= W - 1) best[k] = max(best[k], (C << 8) | (uint32_t)(255 - (t - (W - 1))));
+#pragma unroll
+        for (int z = W - 2; z > 0; --z) ring[k][z] = ring[k][z - 1];
+        ring[k][0] = y[u];
+      }
+    }
   }
+  // hand the keys over to the lanes' pixel groups: the best key of each
+  // pixel (C < 2^21, so bits 29..31 are free) with bit 31 = low gain
+#pragma unroll
+  for (int k = 0; k < MAXK; ++k) {
+    const int i = (int)threadIdx.x + k * NT;
+    if (i < N) keys[i] = best[k] | ((dual && (int)hmax[k] >= c.hg_switch) ? 0x80000000u : 0u);
+  }
+  __syncthreads();
 #pragma unroll
   for (int ps = 0; ps < MAXP; ++ps) {
     if (ps >= npass) continue;
@@ -579,13 +586,14 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
       const int i = pix0 + p;
       key[p] = 0;
       if (i >= N) continue;
-      const int g = dual && (int)hmax[ps][p] >= c.hg_switch ? 1 : 0;
+      const uint32_t kb = keys[i];
+      const int g = (int)(kb >> 31);
       sw |= (uint32_t)g << p;
-      const int s = 255 - (int)(best[ps][p] & 255u);
+      const int s = 255 - (int)(kb & 255u);
       const uint16_t* col = ev + ((size_t)g * T + s) * np + i;
       uint32_t S = 0;
 #pragma unroll
-      for (int k = 0; k < W; ++k) S += col[(size_t)k * np];
+      for (int u = 0; u < W; ++u) S += col[(size_t)u * np];
       key[p] = (S << 8) | (uint32_t)(255 - s);
     }
     fn(pix0, key, sw);
@@ -616,7 +624,7 @@ __device__ __forceinline__ void extract_event(const DevCam& c, __amdgpu_buffer_r
       fn(pix0, key, sw);
     }
   } else if constexpr (EX == kExNeighbour) {
-    neighbour_event<PPL, W, NT>(c, r, ev, xrow, fn);
+    neighbour_event<PPL, W, NT>(c, r, ev, xrow, rows, fn);
   } else {
     constexpr int MAXP = (kMaxPix + NT * PPL - 1) / (NT * PPL);
     uint32_t* my_rows = rows + (threadIdx.x / kWave) * 256;
@@ -1020,7 +1028,7 @@ template <int EX, int PPL, int W, int NT>
 __global__ __launch_bounds__(NT) void k_calibrate(DevCam c, const uint16_t* __restrict__ traces, int32_t* S,
                                                   int32_t* D, uint8_t* sstar, uint8_t* peak, uint8_t* gain,
                                                   float* q, float* t) {
-  __shared__ uint32_t rows[EX == kExGlobal ? NT / kWave * 256 : 1];
+  __shared__ uint32_t rows[EX == kExGlobal ? NT / kWave * 256 : (EX == kExNeighbour ? kMaxPix : 1)];
   __shared__ __attribute__((aligned(16))) uint16_t xrow[EX == kExNeighbour ? kNbrRows * (kMaxPix + 8) : 8];
   __shared__ int32_t start;
   const int64_t e = blockIdx.x;
