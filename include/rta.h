@@ -380,6 +380,12 @@ rta_status rta_mlp_loss_grad(rta_mlp* m, const float* x, const float* label, con
  * bf16 copies.  loss: device scalar (NULLABLE). */
 rta_status rta_mlp_train_step(rta_mlp* m, const float* x, const float* label, const float* log10e, int64_t B,
                               float* loss, rta_stream stream);
+/* The same step on a batch drawn from data arrays: x [n_data][10], label
+ * [n_data], log10e [n_data] and rows [B] (all DEVICE); batch row b is data
+ * row rows[b] (values outside [0, n_data) are clamped into it), gathered
+ * inside the kernel.  Equal to rta_mlp_train_step on the gathered arrays. */
+rta_status rta_mlp_train_step_rows(rta_mlp* m, const float* x, const float* label, const float* log10e,
+                                   int64_t n_data, const int64_t* rows, int64_t B, float* loss, rta_stream stream);
 
 /* ------------------------------------------------------------------------
  * Classification with fallback.  Plain scaled-width / scaled-length box cuts

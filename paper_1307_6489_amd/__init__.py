@@ -155,6 +155,7 @@ SYMBOLS = {
     "rta_mlp_forward": ([_vp, _vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_mlp_loss_grad": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp], ctypes.c_int),
     "rta_mlp_train_step": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
+    "rta_mlp_train_step_rows": ([_vp, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_features": ([_vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_classify": ([_vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_pipeline_attach_mlp": ([_vp, _vp, _vp], ctypes.c_int),
@@ -633,10 +634,20 @@ class Mlp:
                                        _stream(stream)))
         return loss, grad
 
-    def train_step(self, x, label, log10e, loss_out=None, stream=None):
-        B = self._batch(x, label, log10e)
-        _check(lib().rta_mlp_train_step(self.handle, _ptr(x), _ptr(label), _ptr(log10e), B, _ptr(loss_out),
-                                        _stream(stream)))
+    def train_step(self, x, label, log10e, loss_out=None, stream=None, rows=None):
+        """One Adam step on the batch (x, label, log10e); with ``rows`` (int64
+        device tensor) the batch is rows of those data arrays, gathered in the
+        kernel."""
+        if rows is None:
+            B = self._batch(x, label, log10e)
+            _check(lib().rta_mlp_train_step(self.handle, _ptr(x), _ptr(label), _ptr(log10e), B, _ptr(loss_out),
+                                            _stream(stream)))
+            return
+        import torch
+        n = self._batch(x, label, log10e)
+        _require(rows, torch.int64, name="rows")
+        _check(lib().rta_mlp_train_step_rows(self.handle, _ptr(x), _ptr(label), _ptr(log10e), n, _ptr(rows),
+                                             rows.numel(), _ptr(loss_out), _stream(stream)))
 
 
 def features(rec, stream=None):

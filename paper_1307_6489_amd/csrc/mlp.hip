@@ -18,6 +18,7 @@
 #include <cmath>
 
 #include "mlp_device.h"
+#include "mlp_launch.h"
 
 namespace rta {
 using namespace mlpdev;
@@ -25,19 +26,40 @@ constexpr int kRowsNT = 256;  // 4 wavefronts, 16 rows each
 
 namespace {
 
+// Standardised input tile of batch rows r0..r0+15 taken from data rows
+// rows[b] (clamped to [0, n_data)) of x [n_data][10].
+__device__ __forceinline__ bf16x4 gather_input_tile(const MlpDev& w, const float* x, const int64_t* rows,
+                                                    int64_t n_data, int B, int r0) {
+  const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+  const int b = r0 + col;
+  int64_t d = 0;
+  if (b < B) d = min(max(rows[b], (int64_t)0), n_data - 1);
+  float v[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int f = 4 * grp + j;
+    v[j] = (b < B && f < kIn) ? (x[d * kIn + f] - w.mean[f]) / w.stdv[f] : 0.f;
+  }
+  return pack4(v[0], v[1], v[2], v[3]);
+}
+
 // Forward (+ loss, + backward to every layer's pre-activation gradient when
-// TRAIN) of 16-row tiles, one per wavefront.
+// TRAIN) of 16-row tiles, one per wavefront.  rows != null: batch row b is
+// data row rows[b] of x / label / log10e (the batch gather done here
+// instead of in separate copies).
 template <bool TRAIN>
 __global__ __launch_bounds__(kRowsNT) void k_mlp_rows(MlpDev w, const float* __restrict__ x,
                                                       const float* __restrict__ label,
-                                                      const float* __restrict__ log10e, int B, int Bpad,
-                                                      float* __restrict__ out) {
+                                                      const float* __restrict__ log10e,
+                                                      const int64_t* __restrict__ rows, int64_t n_data, int B,
+                                                      int Bpad, float* __restrict__ out) {
   const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
   const int r0 = (blockIdx.x * (kRowsNT / 64) + (threadIdx.x >> 6)) * 16;
   if (r0 >= Bpad) return;
   const int b = r0 + col;
   const bool valid = b < B;
-  const bf16x4 xin = mlp_input_tile(w, x, B, r0);
+  const bf16x4 xin = rows ? gather_input_tile(w, x, rows, n_data, B, r0) : mlp_input_tile(w, x, B, r0);
+  const int64_t db = (rows && valid) ? min(max(rows[b], (int64_t)0), n_data - 1) : (int64_t)b;
   bf16x4 h1[4], h2[4], h3[4];
   const f32x4 o = mlp_forward_tile(w, xin, h1, h2, h3);
   if (!TRAIN) {
@@ -52,7 +74,7 @@ __global__ __launch_bounds__(kRowsNT) void k_mlp_rows(MlpDev w, const float* __r
   if (grp == 0) {
     float lrow = 0.f;
     if (valid) {
-      const float z = o[0], e = o[1], lab = label[b], y = log10e[b];
+      const float z = o[0], e = o[1], lab = label[db], y = log10e[db];
       const float m = lab > 0.5f ? 1.f : 0.f;
       const float sig = 1.f / (1.f + expf(-z));
       lrow = fmaxf(z, 0.f) - z * lab + log1pf(expf(-fabsf(z))) + m * (e - y) * (e - y);
@@ -253,12 +275,20 @@ __global__ __launch_bounds__(256) void k_mlp_adam(MlpDev w, int update, float lr
 
 hipError_t launch_mlp_rows(const MlpDev& w, const float* x, const float* label, const float* log10e, int B, int Bpad,
                            float* out, bool train, hipStream_t st) {
+  return launch_mlp_rows_gather(w, x, label, log10e, nullptr, 0, B, Bpad, out, train, st);
+}
+
+hipError_t launch_mlp_rows_gather(const MlpDev& w, const float* x, const float* label, const float* log10e,
+                                  const int64_t* rows, int64_t n_data, int B, int Bpad, float* out, bool train,
+                                  hipStream_t st) {
   const int tiles = Bpad / 16;
   const int grid = (tiles + 3) / 4;
   if (train)
-    hipLaunchKernelGGL(k_mlp_rows<true>, dim3(grid), dim3(kRowsNT), 0, st, w, x, label, log10e, B, Bpad, out);
+    hipLaunchKernelGGL(k_mlp_rows<true>, dim3(grid), dim3(kRowsNT), 0, st, w, x, label, log10e, rows, n_data, B,
+                       Bpad, out);
   else
-    hipLaunchKernelGGL(k_mlp_rows<false>, dim3(grid), dim3(kRowsNT), 0, st, w, x, label, log10e, B, Bpad, out);
+    hipLaunchKernelGGL(k_mlp_rows<false>, dim3(grid), dim3(kRowsNT), 0, st, w, x, label, log10e, rows, n_data, B,
+                       Bpad, out);
   return hipGetLastError();
 }
 

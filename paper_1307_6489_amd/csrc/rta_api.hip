@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "mlp_launch.h"
 #include "rta_internal.h"
 
 struct rta_camera {
@@ -847,21 +848,29 @@ rta_status rta_mlp_forward(rta_mlp* m, const float* x, int64_t B, float* out, rt
   return RTA_OK;
 }
 
-static rta_status mlp_loss_grad(rta_mlp* m, const float* x, const float* label, const float* log10e, int64_t B,
-                                float* loss, hipStream_t st) {
+static rta_status mlp_loss_grad(rta_mlp* m, const float* x, const float* label, const float* log10e,
+                                const int64_t* rows, int64_t n_data, int64_t B, float* loss, hipStream_t st) {
   if (!m) return fail(RTA_E_INVALID_ARG, "null network");
   if (!m->has_params) return fail(RTA_E_INVALID_ARG, "network parameters not set");
   if (B < 1 || B > m->max_batch) return fail(RTA_E_SHAPE, "batch must be in [1, max_batch]");
   if (!x || !label || !log10e) return fail(RTA_E_INVALID_ARG, "null input");
   const int Bpad = (int)((B + 63) & ~63LL);
-  RTA_HIP(rta::launch_mlp_rows(m->dev, x, label, log10e, (int)B, Bpad, nullptr, true, st));
+  RTA_HIP(rta::launch_mlp_rows_gather(m->dev, x, label, log10e, rows, n_data, (int)B, Bpad, nullptr, true, st));
   RTA_HIP(rta::launch_mlp_grad(m->dev, (int)B, Bpad, loss, st));
+  return RTA_OK;
+}
+
+static rta_status mlp_adam(rta_mlp* m, hipStream_t st) {
+  m->step += 1;
+  const double c1 = 1.0 / (1.0 - std::pow((double)m->beta1, (double)m->step));
+  const double c2 = 1.0 / (1.0 - std::pow((double)m->beta2, (double)m->step));
+  RTA_HIP(rta::launch_mlp_adam(m->dev, true, m->lr, m->beta1, m->beta2, m->eps, (float)c1, (float)c2, st));
   return RTA_OK;
 }
 
 rta_status rta_mlp_loss_grad(rta_mlp* m, const float* x, const float* label, const float* log10e, int64_t B,
                              float* grad, float* loss, rta_stream stream) {
-  rta_status s = mlp_loss_grad(m, x, label, log10e, B, loss, (hipStream_t)stream);
+  rta_status s = mlp_loss_grad(m, x, label, log10e, nullptr, 0, B, loss, (hipStream_t)stream);
   if (s != RTA_OK) return s;
   RTA_HIP(rta::launch_mlp_grad_sum(m->dev, (hipStream_t)stream));
   if (grad)
@@ -872,14 +881,18 @@ rta_status rta_mlp_loss_grad(rta_mlp* m, const float* x, const float* label, con
 
 rta_status rta_mlp_train_step(rta_mlp* m, const float* x, const float* label, const float* log10e, int64_t B,
                               float* loss, rta_stream stream) {
-  rta_status s = mlp_loss_grad(m, x, label, log10e, B, loss, (hipStream_t)stream);
+  rta_status s = mlp_loss_grad(m, x, label, log10e, nullptr, 0, B, loss, (hipStream_t)stream);
   if (s != RTA_OK) return s;
-  m->step += 1;
-  const double c1 = 1.0 / (1.0 - std::pow((double)m->beta1, (double)m->step));
-  const double c2 = 1.0 / (1.0 - std::pow((double)m->beta2, (double)m->step));
-  RTA_HIP(rta::launch_mlp_adam(m->dev, true, m->lr, m->beta1, m->beta2, m->eps, (float)c1, (float)c2,
-                               (hipStream_t)stream));
-  return RTA_OK;
+  return mlp_adam(m, (hipStream_t)stream);
+}
+
+rta_status rta_mlp_train_step_rows(rta_mlp* m, const float* x, const float* label, const float* log10e,
+                                   int64_t n_data, const int64_t* rows, int64_t B, float* loss, rta_stream stream) {
+  if (n_data < 1) return fail(RTA_E_SHAPE, "n_data must be >= 1");
+  if (!rows) return fail(RTA_E_INVALID_ARG, "null rows");
+  rta_status s = mlp_loss_grad(m, x, label, log10e, rows, n_data, B, loss, (hipStream_t)stream);
+  if (s != RTA_OK) return s;
+  return mlp_adam(m, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -93,8 +93,7 @@ def train(data, dev, epochs=10, batch=4096, lr=1e-3, seed=3, log=None):
     for ep in range(epochs):
         perm = torch.from_numpy(rng.permutation(n)).to(dev)
         for s in range(0, n - batch + 1, batch):
-            idx = perm[s:s + batch]
-            net.train_step(X[idx].contiguous(), L[idx].contiguous(), E[idx].contiguous(), loss_out=loss)
+            net.train_step(X, L, E, loss_out=loss, rows=perm[s:s + batch])
             steps += 1
         history.append(float(loss.cpu()[0]))
         if log:

@@ -135,3 +135,40 @@ def test_training_learns_a_separable_problem(dev):
     last = float(loss.cpu()[0])
     say("training loss %.4f -> %.4f" % (first, last))
     assert last < first / 5
+
+
+@pytest.mark.parametrize("B", [1, 100, 4096])
+def test_train_step_gathering_rows(dev, B):
+    """A step on rows of data arrays gathered in the kernel equals, bit for
+    bit, the step on the arrays gathered beforehand: parameters and loss
+    after three steps, with repeated rows and rows outside [0, n) clamped to
+    the first / last row."""
+    import torch
+    say("train step gathering rows B=%d seed 9" % B)
+    n = 5000
+    a, theta, x, lab, y = make(dev, 9, n)
+    b = rta.Mlp(max_batch=n)
+    b.set_params(theta.astype(np.float32), np.zeros(10), np.ones(10))
+    X, L, Y = t(x, dev), t(lab, dev), t(y, dev)
+    rng = np.random.default_rng(B)
+    la, lb = torch.zeros(1, device=dev), torch.zeros(1, device=dev)
+    for step in range(3):
+        rows = rng.integers(-3, n + 3, size=B).astype(np.int64)
+        rows[: B // 4] = rows[B // 2: B // 2 + B // 4]
+        r = np.clip(rows, 0, n - 1)
+        a.train_step(X[r].contiguous(), L[r].contiguous(), Y[r].contiguous(), loss_out=la)
+        b.train_step(X, L, Y, loss_out=lb, rows=torch.from_numpy(rows).to(dev))
+        assert np.array_equal(a.get_params(), b.get_params()), step
+        assert torch.equal(la, lb), step
+
+
+def test_train_step_rows_rejects_bad_args(dev):
+    import torch
+    net, theta, x, lab, y = make(dev, 9, 64)
+    X, L, Y = t(x, dev), t(lab, dev), t(y, dev)
+    with pytest.raises(TypeError):
+        net.train_step(X, L, Y, rows=torch.zeros(8, dtype=torch.int32, device=dev))
+    with pytest.raises(rta.RTAError):
+        net.train_step(X, L, Y, rows=torch.zeros(0, dtype=torch.int64, device=dev))
+    with pytest.raises(rta.RTAError):
+        net.train_step(X, L, Y, rows=torch.zeros(65, dtype=torch.int64, device=dev))
