@@ -462,9 +462,11 @@ __device__ __forceinline__ int global_start(const uint32_t* rows, int T, int32_t
 // stands in for a missing neighbour), so a pixel's neighbours cost one 8-byte
 // read each per four slices, and the per-slice neighbour sums y(t) come from
 // packed dot products.  The next four slices are loaded while the current
-// ones are used.  In this stage lane t takes pixels t, t + NT, ... (so the
-// lanes of one read touch consecutive words); the pixels' best keys then go
-// through LDS to the lanes' PPL-pixel groups.  Each lane keeps, for each of its pixels, the last
+// ones are used.  Words sit at the pixels' lattice-row positions, and in this
+// stage lane t takes positions t, t + NT, ...: the lanes of one read are
+// neighbours along a row, so each direction's neighbour words are (nearly)
+// consecutive; the pixels' best keys then go through LDS to the lanes'
+// PPL-pixel groups.  Each lane keeps, for each of its pixels, the last
 // W-1 sums to form C(t-W+1), the best key (C << 8) | (255 - s) and the raw
 // high-gain maximum (gain decision on the whole trace, as for the sliding
 // window).  Then the pixel's own W samples at its start on its selected gain
@@ -483,19 +485,19 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
   // one (64-bit words: the packed dot of a two-lane vector's second element
   // has been seen compiled onto its first)
   uint64_t* xs = reinterpret_cast<uint64_t*>(xrow);
-  // pixel j = 8 g + m of 16-byte group g lives in word 8 g + (m ^ (g & 7)):
-  // consecutive lanes reading consecutive pixels, and the lanes of one
-  // staging store, each touch distinct banks
+  // position p = 8 g + m lives in word 8 g + (m ^ (g & 7)): consecutive
+  // lanes reading consecutive positions touch distinct banks
   auto slot = [](uint32_t j) { return (j & ~7u) | ((j ^ (j >> 3)) & 7u); };
-  uint32_t nb[MAXK][3];  // six neighbour words per pixel, packed 16-bit slots (Npad if missing)
+  uint32_t nb[MAXK][3];  // six neighbour words per position, packed 16-bit slots (Npad if missing)
   uint32_t ring[MAXK][W - 1];
-  uint32_t best[MAXK], hmax[MAXK];
+  uint32_t best[MAXK], hmax[MAXK], pix[MAXK];
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) {
-    const int i = (int)threadIdx.x + k * NT;
+    const int p = (int)threadIdx.x + k * NT;
     nb[k][0] = nb[k][1] = nb[k][2] = (uint32_t)np * 0x10001u;
-    if (i < N) {
-      const int4 v = *reinterpret_cast<const int4*>(c.nbr + (size_t)i * kNbrCols);
+    pix[k] = 0;
+    if (p < N) {
+      const int4 v = *reinterpret_cast<const int4*>(c.lat + (size_t)p * kNbrCols);
       const uint32_t w3[3] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z};
 #pragma unroll
       for (int h = 0; h < 3; ++h) {
@@ -503,6 +505,7 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
         const uint32_t hi = (w3[h] & 0x80000000u) ? (uint32_t)np : slot(w3[h] >> 16);
         nb[k][h] = lo | (hi << 16);
       }
+      pix[k] = (uint32_t)v.w & 0xffffu;
     }
 #pragma unroll
     for (int u = 0; u < W - 1; ++u) ring[k][u] = 0;
@@ -516,6 +519,14 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
   const int q = threadIdx.x;
   const bool stager = q < np / 8;
   const us2 row_lo = {1, 0}, row_hi = {0, 1};
+  // the words of this thread's eight pixels, at their positions
+  uint32_t dst[8];
+  if (stager) {
+    const int4 lp = *reinterpret_cast<const int4*>(c.lpos + (size_t)q * 8);
+    const uint32_t w4[4] = {(uint32_t)lp.x, (uint32_t)lp.y, (uint32_t)lp.z, (uint32_t)lp.w};
+#pragma unroll
+    for (int m = 0; m < 8; ++m) dst[m] = slot((w4[m >> 1] >> ((m & 1) * 16)) & 0xffffu);
+  }
   u32x4 d[kNbrRows];
   auto load4 = [&](int k0) {
 #pragma unroll
@@ -529,7 +540,7 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const uint32_t sel = (m & 1) ? 0x07060302u : 0x05040100u;  // high / low halfwords
-        xs[q * 8 + (m ^ (q & 7))] = (uint64_t)__builtin_amdgcn_perm(d[1][m >> 1], d[0][m >> 1], sel) |
+        xs[dst[m]] = (uint64_t)__builtin_amdgcn_perm(d[1][m >> 1], d[0][m >> 1], sel) |
                                     ((uint64_t)__builtin_amdgcn_perm(d[3][m >> 1], d[2][m >> 1], sel) << 32);
       }
     }
@@ -537,8 +548,8 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
     if (stager && k0 + kNbrRows < T) load4(k0 + kNbrRows);
 #pragma unroll
     for (int k = 0; k < MAXK; ++k) {
-      const int i = (int)threadIdx.x + k * NT;
-      if (i >= N) continue;
+      const int p = (int)threadIdx.x + k * NT;
+      if (p >= N) continue;
       uint32_t y[kNbrRows] = {0u, 0u, 0u, 0u};
 #pragma unroll
       for (int m = 0; m < 6; ++m) {
@@ -550,7 +561,7 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
         y[2] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v23), row_lo, y[2], false);
         y[3] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v23), row_hi, y[3], false);
       }
-      const uint64_t own = xs[slot((uint32_t)i)];
+      const uint64_t own = xs[slot((uint32_t)p)];
       const uint32_t o01 = (uint32_t)own, o23 = (uint32_t)(own >> 32);
       const uint32_t xo[kNbrRows] = {lo16(o01), hi16(o01), lo16(o23), hi16(o23)};
 #pragma unroll
@@ -572,8 +583,8 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
   // pixel (C < 2^21, so bits 29..31 are free) with bit 31 = low gain
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) {
-    const int i = (int)threadIdx.x + k * NT;
-    if (i < N) keys[i] = best[k] | ((dual && (int)hmax[k] >= c.hg_switch) ? 0x80000000u : 0u);
+    const int p = (int)threadIdx.x + k * NT;
+    if (p < N) keys[pix[k]] = best[k] | ((dual && (int)hmax[k] >= c.hg_switch) ? 0x80000000u : 0u);
   }
   __syncthreads();
 #pragma unroll

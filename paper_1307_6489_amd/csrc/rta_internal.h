@@ -29,6 +29,13 @@ struct DevCam {
   const float* y;          // [Npad] m
   const int16_t* nbr;      // [Npad][8] neighbour indices, -1 padded
   const uint8_t* border;   // [Npad] 1 if fewer than 6 neighbours
+  // The pixels in lattice-row order (rows of equal y, x increasing; any
+  // order is correct, this one keeps neighbours of adjacent entries
+  // adjacent): lat[p] = the six neighbours' positions in that order, one
+  // column per direction (-1 if none), then the pixel index and -1;
+  // lpos[j] = the position of pixel j (j itself for padding pixels).
+  const int16_t* lat;      // [Npad][8]
+  const uint16_t* lpos;    // [Npad]
   // Packet CRC constants of this type (multiplications modulo the CRC
   // polynomial): [0, 256) i*K and [256, 512) i*x^8*K with K = x^(16N), the
   // per-lane finishing factors x^(8 a_l) at [512, 768), then x^(8*body) and

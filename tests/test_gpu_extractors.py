@@ -228,6 +228,44 @@ def test_calibrate_small_cameras(torch_dev, ex):
         calib_parity(ct, tr, torch_dev, ex)
 
 
+def layout_cameras():
+    """Pixel layouts other than the generator's hexagon in distance order:
+    the 61-pixel hexagon numbered at random, a 15 x 15 square grid (four
+    neighbours), one row of 50 pixels, and a 331-pixel hexagon with every
+    pixel moved by up to 0.1 pitch in x and y (its rows no longer share one
+    y).  Neighbours: the oracle's distance rule (<= 1.4 pitch)."""
+    p = dl0sim.PITCH_M
+    rng = np.random.default_rng(31)
+    h = dl0sim.hex_geometry(61)
+    perm = rng.permutation(61)
+    g = np.arange(15) * p
+    gx, gy = np.meshgrid(g, g)
+    j = dl0sim.hex_geometry(331)
+    shapes = [("relabelled hexagon", h.x[perm], h.y[perm]), ("square grid", gx.ravel(), gy.ravel()),
+              ("single row", np.arange(50) * p, np.zeros(50)),
+              ("jittered hexagon", j.x + rng.uniform(-0.1, 0.1, 331) * p, j.y + rng.uniform(-0.1, 0.1, 331) * p)]
+    out = []
+    for name, x, y in shapes:
+        x = np.ascontiguousarray(x, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        n = len(x)
+        geom = dl0sim.Geometry(n, p, x, y, oracle.neighbours(x, y, 1.4 * p), np.zeros((n, 2), np.int32))
+        out.append((name, dl0sim.CameraType(name, n, 40, 2, 5.0, geom=geom)))
+    return out
+
+
+@pytest.mark.parametrize("ex", EXS)
+def test_calibrate_pixel_layouts(torch_dev, ex):
+    """Every extractor against the oracle on the layouts above (random dual-
+    gain traces, switching included): the lattice-row order in which the
+    neighbour peak stages its words must not change any result."""
+    rng = np.random.default_rng(37)
+    for name, ct in layout_cameras():
+        tr = rng.integers(250, 4300, size=(6, 2, 40, ct.n_pix_pad), dtype=np.uint16)
+        say("pixel layout %s (%d px), %s" % (name, ct.n_pix, NAME[ex]))
+        calib_parity(ct, tr, torch_dev, ex)
+
+
 @pytest.mark.parametrize("ex", [rta.EXTRACT_SLIDING] + EXS)
 def test_fused_small_cameras(torch_dev, ex):
     """The fused batch on a mix of 1-, 7- and 61-pixel cameras (random dual-
