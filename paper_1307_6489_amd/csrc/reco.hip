@@ -469,8 +469,10 @@ __device__ __forceinline__ int global_start(const uint32_t* rows, int T, int32_t
 // PPL-pixel groups.  Each lane keeps, for each of its pixels, the last
 // W-1 sums to form C(t-W+1), the best key (C << 8) | (255 - s) and the raw
 // high-gain maximum (gain decision on the whole trace, as for the sliding
-// window).  Then the pixel's own W samples at its start on its selected gain
-// give S.  Called by every thread of the block (contains barriers).
+// window); a step whose four slices all end a window inside the trace forms
+// its four window sums at once.  Then the pixel's own W samples at its start
+// on its selected gain give S.  Called by every thread of the block
+// (contains barriers).
 template <int PPL, int W, int NT, class Fn>
 __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer_rsrc_t r,
                                                 const uint16_t* __restrict__ ev, uint16_t* xrow, uint32_t* keys,
@@ -490,7 +492,7 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
   auto slot = [](uint32_t j) { return (j & ~7u) | ((j ^ (j >> 3)) & 7u); };
   uint32_t nb[MAXK][3];  // six neighbour words per position, packed 16-bit slots (Npad if missing)
   uint32_t ring[MAXK][W - 1];
-  uint32_t best[MAXK], hmax[MAXK], pix[MAXK];
+  uint32_t best[MAXK], hmax[MAXK], hmax2[MAXK], pix[MAXK];
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) {
     const int p = (int)threadIdx.x + k * NT;
@@ -511,6 +513,7 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
     for (int u = 0; u < W - 1; ++u) ring[k][u] = 0;
     best[k] = 0;
     hmax[k] = 0;
+    hmax2[k] = 0;
   }
   if (threadIdx.x == 0) xs[np] = 0ull;
   // thread q stages 16-byte pixel group q (np / 8 <= kMaxPix / 8 <= NT
@@ -546,6 +549,9 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
     }
     __syncthreads();
     if (stager && k0 + kNbrRows < T) load4(k0 + kNbrRows);
+    // uniform: every slice of this step has a full window inside the trace
+    const bool full = k0 >= W - 1 && k0 + kNbrRows <= T;
+    const uint32_t key0 = (uint32_t)(255 - (k0 - (W - 1)));  // 255 - window start of slice k0
 #pragma unroll
     for (int k = 0; k < MAXK; ++k) {
       const int p = (int)threadIdx.x + k * NT;
@@ -563,6 +569,27 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
       }
       const uint64_t own = xs[slot((uint32_t)p)];
       const uint32_t o01 = (uint32_t)own, o23 = (uint32_t)(own >> 32);
+      if constexpr (W == kNbrRows) if (full) {
+        // all four slices inside the trace and past the first window: the
+        // four window sums C(k0 + u) = y(k0 + u - 3) + ... + y(k0 + u) from
+        // the ring (ring[z] = y(k0 - 1 - z)) and this step's sums, the
+        // ring shifted once, the high-gain maximum on packed halfwords
+        const us2 hm = __builtin_elementwise_max(
+            __builtin_elementwise_max(__builtin_bit_cast(us2, hmax2[k]), __builtin_bit_cast(us2, o01)),
+            __builtin_bit_cast(us2, o23));
+        hmax2[k] = __builtin_bit_cast(uint32_t, hm);
+        const uint32_t r01 = ring[k][0] + ring[k][1], y01 = y[0] + y[1];
+        const uint32_t C0 = y[0] + r01 + ring[k][2], C1 = y[1] + y[0] + r01;
+        const uint32_t C2 = y[2] + y01 + ring[k][0], C3 = y[3] + y[2] + y01;
+        best[k] = max(best[k], (C0 << 8) | key0);
+        best[k] = max(best[k], (C1 << 8) | (key0 - 1u));
+        best[k] = max(best[k], (C2 << 8) | (key0 - 2u));
+        best[k] = max(best[k], (C3 << 8) | (key0 - 3u));
+        ring[k][0] = y[3];
+        ring[k][1] = y[2];
+        ring[k][2] = y[1];
+        continue;
+      }
       const uint32_t xo[kNbrRows] = {lo16(o01), hi16(o01), lo16(o23), hi16(o23)};
 #pragma unroll
       for (int u = 0; u < kNbrRows; ++u) {
@@ -584,7 +611,8 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) {
     const int p = (int)threadIdx.x + k * NT;
-    if (p < N) keys[pix[k]] = best[k] | ((dual && (int)hmax[k] >= c.hg_switch) ? 0x80000000u : 0u);
+    const uint32_t hm = max(hmax[k], max(lo16(hmax2[k]), hi16(hmax2[k])));
+    if (p < N) keys[pix[k]] = best[k] | ((dual && (int)hm >= c.hg_switch) ? 0x80000000u : 0u);
   }
   __syncthreads();
 #pragma unroll
