@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "lattice.h"
 #include "mlp_launch.h"
 #include "rta_internal.h"
 
@@ -114,57 +115,6 @@ void crc_tables(int N, int T, int G, uint16_t* t) {
 
 void fill_event_args(const rta_pipeline* pipe, rta::EventArgs& ea);
 
-// Lattice-row order of the pixels for the neighbour-peak gathers: rows of
-// equal y (quantised to half the smallest neighbour distance), x increasing,
-// ties by index.  lat[p] holds the positions of the neighbours of the pixel
-// at position p, one column per direction (0/1: row before, x below / above;
-// 2/3: same row; 4/5: row after; a neighbour whose column is taken goes to
-// the first free one), then the pixel index.  Only the speed of the gathers
-// depends on this order.
-void lattice_order(int N, int Np, const float* X, const float* Y, const int16_t* nb, int16_t* lat, uint16_t* lpos) {
-  double pitch = 0.0;
-  for (int i = 0; i < N; ++i)
-    for (int k = 0; k < rta::kNbrCols; ++k) {
-      const int j = nb[(size_t)i * rta::kNbrCols + k];
-      if (j < 0) continue;
-      const double d = std::hypot((double)X[j] - X[i], (double)Y[j] - Y[i]);
-      if (std::isfinite(d) && d > 0.0 && (pitch == 0.0 || d < pitch)) pitch = d;
-    }
-  const double q = pitch > 0.0 ? 0.5 * pitch : 1.0;
-  auto fin = [](double v) { return std::isfinite(v) ? std::min(std::max(v, -1e15), 1e15) : 0.0; };
-  std::vector<long long> row(N);
-  std::vector<double> xk(N);
-  for (int i = 0; i < N; ++i) {
-    row[i] = std::llround(fin((double)Y[i] / q));
-    xk[i] = fin((double)X[i]);
-  }
-  std::vector<int> order(N);
-  for (int i = 0; i < N; ++i) order[i] = i;
-  std::sort(order.begin(), order.end(), [&](int a, int b) {
-    if (row[a] != row[b]) return row[a] < row[b];
-    if (xk[a] != xk[b]) return xk[a] < xk[b];
-    return a < b;
-  });
-  std::vector<int> pos(N);
-  for (int p = 0; p < N; ++p) pos[order[p]] = p;
-  for (int j = 0; j < Np; ++j) lpos[j] = (uint16_t)(j < N ? pos[j] : j);
-  for (int p = 0; p < N; ++p) {
-    const int i = order[p];
-    int16_t* L = lat + (size_t)p * rta::kNbrCols;
-    for (int k = 0; k < rta::kNbrCols; ++k) {
-      const int j = nb[(size_t)i * rta::kNbrCols + k];
-      if (j < 0) continue;
-      const int dc = row[j] < row[i] ? 0 : (row[j] == row[i] ? 2 : 4);
-      int col = dc + (xk[j] > xk[i] ? 1 : 0);
-      if (L[col] >= 0) {
-        col = 0;
-        while (col < 6 && L[col] >= 0) ++col;
-      }
-      L[col] = (int16_t)pos[j];  // at most six neighbours, so a column is free
-    }
-    L[6] = (int16_t)i;
-  }
-}
 
 rta_status launch_batch(rta_pipeline* pipe, const rta_batch* b, rta_hillas_rec* tel_out, rta_event_rec* evt_out,
                         hipStream_t st) {
@@ -297,9 +247,10 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
     }
     border[i] = cnt < 6 ? 1 : 0;
   }
+  static_assert(rta::kLatCols == rta::kNbrCols, "lattice rows share the neighbour table's width");
   std::vector<int16_t> lat(Np * rta::kNbrCols, -1);
   std::vector<uint16_t> lpos(Np, 0);
-  lattice_order(N, Np, X.data(), Y.data(), nb.data(), lat.data(), lpos.data());
+  rta::lattice_order(N, Np, X.data(), Y.data(), nb.data(), lat.data(), lpos.data());
   // one device allocation, 256-byte aligned sub-arrays
   const size_t oP = 0, oTp = oP + round256(P.size() * 4), oTb = oTp + round256(Tp.size() * 4);
   const size_t oA = oTb + round256(Tb.size() * 4), oX = oA + round256(A.size() * 4);
