@@ -92,3 +92,39 @@ def test_adam_first_step_moves_by_lr_times_sign():
     g = np.array([0.3, -2.0, 1e-3, -1e-2, 5.0])
     new = opt.step(theta, g)
     assert np.allclose(new, -1e-3 * np.sign(g), rtol=1e-4)
+
+
+def _record(**kw):
+    dt = np.dtype([(f, "<f8") for f in ("size", "cog_x", "cog_y", "length", "width", "psi", "skewness",
+                                         "kurtosis", "time_gradient", "time_intercept", "leakage", "cog_dist")]
+                  + [("n_pix", "<i8"), ("n_islands", "<i8"), ("n_lowgain", "<i8"), ("flags", "<i8")])
+    r = np.zeros(1, dt)
+    for k, v in kw.items():
+        r[k] = v
+    return r
+
+
+def test_features_from_records_hand_record():
+    """The network input of one hand-written record, every field distinct:
+    the ten columns in the documented order log10(size), length, width,
+    cog distance, psi, skewness, kurtosis, time gradient, leakage, islands
+    (log10(1000) = 3); fields the network does not read stay out."""
+    r = _record(size=1000.0, cog_x=9.1, cog_y=9.2, length=0.11, width=0.022, psi=0.44, skewness=0.55,
+                kurtosis=2.66, time_gradient=7.77, time_intercept=9.3, leakage=0.088, cog_dist=0.33,
+                n_pix=91, n_islands=3, n_lowgain=94, flags=0)
+    x = mlp.features_from_records(r)
+    assert x.shape == (1, 10)
+    assert x[0].tolist() == [3.0, 0.11, 0.022, 0.33, 0.44, 0.55, 2.66, 7.77, 0.088, 3.0]
+    assert mlp.FEATURES[0] == "log10_size" and mlp.FEATURES[9] == "n_islands"
+
+
+def test_features_from_records_log_size_edges():
+    """log10 of the size: exact at powers of ten, -inf at 0, NaN below 0 and
+    for a NaN size, so such records can never look in range."""
+    sizes = [1e5, 10.0, 0.0, -5.0, float("nan")]
+    r = np.concatenate([_record(size=s, length=0.1) for s in sizes])
+    x = mlp.features_from_records(r)
+    assert x[0, 0] == 5.0 and x[1, 0] == 1.0
+    assert x[2, 0] == -math.inf
+    assert math.isnan(x[3, 0]) and math.isnan(x[4, 0])
+    assert np.all(x[:, 1] == 0.1)

@@ -524,3 +524,69 @@ def test_philox_known_answers():
         ["0x6627e8d5", "0xe169c58d", "0xbc57ac4c", "0x9b00dbd8"]
     assert [hex(v) for v in dl0sim.philox4x32_10([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2)] == \
         ["0x408f276d", "0x41c83b0e", "0xa20bc7c6", "0x6d5451fd"]
+
+
+# ---------------------------------------------------------------- cog distance, low-gain count
+def test_cog_distance_hand_cases():
+    """cog distance is the distance of the charge-weighted centre from the
+    camera centre.  Charges 2 and 1 at (0, 0) and (0.09, 0.12) m put the
+    centre at (0.03, 0.04): distance 0.05, not the rms radius of the pixels
+    (0.05 sqrt(3) = 0.0866) nor the mean pixel distance (0.05).  A third,
+    bright pixel outside the mask does not move it; two charges placed
+    symmetrically about (0.03, 0.04) give 0.05 as well."""
+    xs = np.array([0.0, 0.09, -0.4], np.float32)
+    ys = np.array([0.0, 0.12, 0.3], np.float32)
+    cam = point_cam(xs, ys)
+    h = cam.hillas([2.0, 1.0, 50.0], [0.0, 0.0, 0.0], [1, 1, 0])
+    cx = (2 * float(xs[0]) + float(xs[1])) / 3
+    cy = (2 * float(ys[0]) + float(ys[1])) / 3
+    assert h["cog_x"] == pytest.approx(0.03, rel=1e-7) and h["cog_y"] == pytest.approx(0.04, rel=1e-7)
+    assert h["cog_dist"] == pytest.approx(math.hypot(cx, cy), rel=1e-12)
+    assert h["cog_dist"] == pytest.approx(0.05, rel=1e-7)
+    xs = np.array([0.03 - 0.2, 0.03 + 0.2], np.float32)
+    ys = np.array([0.04 + 0.1, 0.04 - 0.1], np.float32)
+    h = point_cam(xs, ys).hillas([1.0, 1.0], [0.0, 0.0], [1, 1])
+    assert h["cog_dist"] == pytest.approx(0.05, rel=1e-6)
+
+
+def test_low_gain_count_over_all_pixels():
+    """n_lowgain counts the pixels that used their low gain over the whole
+    camera, inside and outside the cleaning mask, and the low-gain flag is
+    set exactly when that count is non-zero."""
+    g = dl0sim.hex_geometry(19)
+    cam = geometry_cam(g, G=2)
+    q = np.linspace(1.0, 3.0, 19)
+    t = np.zeros(19)
+    mask = np.zeros(19, np.uint8)
+    mask[[0, 1, 2, 3]] = 1
+    gain = np.zeros(19, np.int32)
+    h = cam.hillas(q, t, mask, gain)
+    assert h["n_lowgain"] == 0 and not h["flags"] & oracle.LOW_GAIN
+    gain[[2, 7, 11, 18]] = 1          # one inside the mask, three outside
+    h = cam.hillas(q, t, mask, gain)
+    assert h["n_lowgain"] == 4 and h["flags"] & oracle.LOW_GAIN
+    mask[:] = 0                       # empty mask: still counted, still flagged
+    h = cam.hillas(q, t, mask, gain)
+    assert h["n_lowgain"] == 4 and h["flags"] & oracle.LOW_GAIN and h["flags"] & oracle.HILLAS_INVALID
+
+
+def test_low_gain_count_through_the_chain():
+    """Whole-event reconstruction of a dual-gain event: with k pixels forced
+    over the switch (most of them far from the image, so outside the mask)
+    the record counts k and is flagged; with none forced, 0 and no flag."""
+    types = dl0sim.camera_types_c1()
+    ct = types[1]
+    sh = dl0sim.draw_ellipses(dl0sim.draw_cfg_plain(ct.n_samp), 1, 0, 5)
+    sh["size"][:, 0] = 400.0
+    tr = dl0sim.render_traces(ct, sh, 5)
+    ev = tr[0].copy()
+    assert ev[0].max() < ct.hg_switch_adc
+    od = oracle.Camera.from_type(ct)
+    _, m0, h0 = od.reconstruct(ev)
+    assert h0["n_lowgain"] == 0 and not h0["flags"] & oracle.LOW_GAIN
+    forced = np.array([5, 77, 400, 901, 1500, 1763])
+    ev[0, 2, forced] = ct.hg_switch_adc
+    pix, m1, h1 = od.reconstruct(ev)
+    assert np.all(pix["gain"][forced] == 1) and int(np.sum(pix["gain"])) == len(forced)
+    assert int(np.sum(m1[forced])) < len(forced)
+    assert h1["n_lowgain"] == len(forced) and h1["flags"] & oracle.LOW_GAIN
