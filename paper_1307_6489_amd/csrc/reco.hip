@@ -27,6 +27,7 @@
 #include <cfloat>
 #include <cmath>
 
+#include "descriptors.h"
 #include "mlp_device.h"
 #include "rta_internal.h"
 
@@ -1153,22 +1154,16 @@ template <int EX, int PPL, int W, int CH, int NT>
 __device__ __forceinline__ void fused_telescope(const FusedArgs& a, long long tel, TelSmem& sm) {
   const int ty = uniform_i32(a.tel_type[tel]);
   const long long off = uniform_i64(a.tel_trace_off[tel]);
-  if (ty < 0 || ty >= a.n_types) {
+  const uint32_t bad = tel_descriptor_status(ty, off, a.n_types, a.traces_len,
+                                             [&](int t) { return (int64_t)a.cams[t].event_elems; });
+  if (bad) {
     if (threadIdx.x == 0) {
       bad_record(a.out + tel);
-      atomicOr(a.status, RTA_STATUS_BAD_TYPE);
+      atomicOr(a.status, bad);
     }
     return;
   }
-  const DevCam& c = a.cams[ty];
-  if (off < 0 || (off & 7) || off + c.event_elems > a.traces_len) {
-    if (threadIdx.x == 0) {
-      bad_record(a.out + tel);
-      atomicOr(a.status, RTA_STATUS_BAD_OFFSET);
-    }
-    return;
-  }
-  process_telescope<EX, PPL, W, CH, NT>(c, uniform_ptr(a.traces + off), sm, a.out + tel);
+  process_telescope<EX, PPL, W, CH, NT>(a.cams[ty], uniform_ptr(a.traces + off), sm, a.out + tel);
 }
 
 // Persistent form: a fixed grid of workgroups pulls telescopes from a global
@@ -1209,7 +1204,7 @@ __global__ __launch_bounds__(kEvtNT) void k_event(EventArgs a) {
   rta_event_rec r;
   r.gammaness = kNaN;
   r.log10_energy = kNaN;
-  if (lo < 0 || hi < lo || hi > a.n_tel) {
+  if (!event_range_ok(lo, hi, a.n_tel)) {
     if (lane == 0) {
       r.dir_x = r.dir_y = r.cond = kNaN;
       r.n_tel = 0;
