@@ -254,6 +254,29 @@ rta_status rta_list_schedules(rta_schedule* out, int32_t cap, int32_t* n);
 rta_status rta_process_batch(rta_pipeline* pipe, const rta_batch* batch, rta_hillas_rec* tel_out,
                              rta_event_rec* evt_out, rta_stream stream);
 
+/* Allocation-free form of rta_process_batch, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same kernels, arguments, checks and
+ * records as rta_process_batch with the pipeline pipe (its cameras, params,
+ * schedule and attached network); the work-queue counter and the status word
+ * live in a static device array of RTA_NOALLOC_SCRATCH_BYTES bytes, one per
+ * GPU, held until the process ends, instead of the pipeline's device memory.
+ * The call allocates nothing (no hipMalloc / hipFree, no allocating library
+ * routine); its first call on a device looks up that device's copy of the
+ * array.  The scratch need is fixed (a 64-bit counter and a 32-bit word,
+ * within the 256 bytes) and does not grow with the batch, so batches are
+ * limited exactly as for rta_process_batch.
+ * status_out: NULLABLE device uint32; receives, on the stream, the
+ * RTA_STATUS_* bits of this call's batch alone (the scratch status word is
+ * cleared at the start of the call; the pipeline's own status word is not
+ * touched).  The pipeline's device must be the current device, else
+ * RTA_E_INVALID_ARG.  Every call on one GPU shares that GPU's scratch: calls
+ * that overlap on one GPU (different streams or threads) race and must not be
+ * issued. */
+#define RTA_NOALLOC_SCRATCH_BYTES 256
+rta_status rta_process_batch_noalloc(const rta_pipeline* pipe, const rta_batch* batch, rta_hillas_rec* tel_out,
+                                     rta_event_rec* evt_out, uint32_t* status_out, rta_stream stream);
+
 /* Stereo per array event from existing telescope records, using the
  * pipeline's focal lengths and cuts.  evt_tel_off [n_evt+1] (values in
  * [0, n_tel]), tel_type [n_tel], tel [n_tel], evt_out [n_evt]. */

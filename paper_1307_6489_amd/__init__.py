@@ -134,6 +134,7 @@ SYMBOLS = {
     "rta_get_schedule": ([_vp, _vp], ctypes.c_int),
     "rta_list_schedules": ([_vp, _i32, _vp], ctypes.c_int),
     "rta_process_batch": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "rta_process_batch_noalloc": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "rta_stereo": ([_vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
     "rta_batch_status": ([_vp, _vp], ctypes.c_int),
     "rta_graph_capture": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
@@ -394,6 +395,12 @@ class Pipeline:
     def process(self, batch, tel_out, evt_out=None, stream=None):
         _check(lib().rta_process_batch(self.handle, ctypes.byref(batch), _ptr(tel_out), _ptr(evt_out),
                                        _stream(stream)))
+
+    def process_noalloc(self, batch, tel_out, evt_out=None, status_out=None, stream=None):
+        """rta_process_batch_noalloc: the same batch through the library's
+        static scratch (status_out: optional device uint32 tensor [1])."""
+        _check(lib().rta_process_batch_noalloc(self.handle, ctypes.byref(batch), _ptr(tel_out), _ptr(evt_out),
+                                               _ptr(status_out), _stream(stream)))
 
     def stereo(self, evt_tel_off, tel_type, tel_rec, stream=None):
         import torch

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -116,8 +117,52 @@ void crc_tables(int N, int T, int G, uint16_t* t) {
 void fill_event_args(const rta_pipeline* pipe, rta::EventArgs& ea);
 
 
-rta_status launch_batch(rta_pipeline* pipe, const rta_batch* b, rta_hillas_rec* tel_out, rta_event_rec* evt_out,
-                        hipStream_t st) {
+// Scratch of rta_process_batch_noalloc: the work-queue counter at byte
+// kScratchQueue and the status word at byte kScratchStatus.  One copy per GPU
+// (the runtime places a device variable on every device that loads the
+// library), held until the process ends.  Host code never uses the name
+// `scratch` as an address: noalloc_scratch() resolves each device's copy once.
+constexpr size_t kScratchQueue = 0, kScratchStatus = 64;
+static_assert(kScratchStatus + sizeof(uint32_t) <= RTA_NOALLOC_SCRATCH_BYTES, "scratch layout exceeds its size");
+static __device__ __align__(256) uint8_t scratch[RTA_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (which must be current): looked
+// up by hipGetSymbolAddress on the first call for that device, then cached.
+rta_status noalloc_scratch(int dev, uint8_t** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(RTA_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(RTA_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<uint8_t*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return RTA_OK;
+}
+
+// Clears the counter and the status word of a scratch copy (a kernel, not a
+// memset, so that the call can be captured into a graph).
+__global__ void k_scratch_reset(unsigned long long* queue, uint32_t* status) {
+  if (threadIdx.x == 0) {
+    *queue = 0ull;
+    *status = 0u;
+  }
+}
+
+__global__ void k_status_copy(const uint32_t* status, uint32_t* out) {
+  if (threadIdx.x == 0) *out = *status;
+}
+
+// Launches of one batch; queue: the work-queue counter, status: the status
+// word the kernels OR their RTA_STATUS_* bits into.
+rta_status launch_batch(const rta_pipeline* pipe, const rta_batch* b, rta_hillas_rec* tel_out,
+                        rta_event_rec* evt_out, unsigned long long* queue, uint32_t* status, hipStream_t st) {
   rta::FusedArgs fa;
   std::memset(&fa, 0, sizeof(fa));
   for (size_t i = 0; i < pipe->cams.size(); ++i) fa.cams[i] = pipe->cams[i]->dev;
@@ -131,10 +176,10 @@ rta_status launch_batch(rta_pipeline* pipe, const rta_batch* b, rta_hillas_rec* 
   fa.tel_trace_off = b->tel_trace_off;
   fa.n_tel = b->n_tel;
   fa.out = tel_out;
-  fa.queue = pipe->d_queue;
-  fa.status = pipe->d_status;
+  fa.queue = queue;
+  fa.status = status;
   if (b->n_tel > 0) {
-    RTA_HIP(rta::launch_queue_reset(pipe->d_queue, st));
+    RTA_HIP(rta::launch_queue_reset(queue, st));
     RTA_HIP(rta::launch_fused(fa, pipe->sched, pipe->n_cu, st));
   }
   if (pipe->params.do_stereo && b->n_evt > 0) {
@@ -146,7 +191,7 @@ rta_status launch_batch(rta_pipeline* pipe, const rta_batch* b, rta_hillas_rec* 
     ea.n_tel = b->n_tel;
     ea.tel = tel_out;
     ea.out = evt_out;
-    ea.status = pipe->d_status;
+    ea.status = status;
     RTA_HIP(rta::launch_event(ea, st));
   }
   return RTA_OK;
@@ -441,7 +486,31 @@ rta_status rta_process_batch(rta_pipeline* pipe, const rta_batch* batch, rta_hil
                              rta_event_rec* evt_out, rta_stream stream) {
   rta_status s = check_batch(pipe, batch, tel_out, evt_out);
   if (s != RTA_OK) return s;
-  return launch_batch(pipe, batch, tel_out, evt_out, (hipStream_t)stream);
+  return launch_batch(pipe, batch, tel_out, evt_out, pipe->d_queue, pipe->d_status, (hipStream_t)stream);
+}
+
+rta_status rta_process_batch_noalloc(const rta_pipeline* pipe, const rta_batch* batch, rta_hillas_rec* tel_out,
+                                     rta_event_rec* evt_out, uint32_t* status_out, rta_stream stream) {
+  rta_status s = check_batch(pipe, batch, tel_out, evt_out);
+  if (s != RTA_OK) return s;
+  int dev = -1;
+  RTA_HIP(hipGetDevice(&dev));
+  if (dev != pipe->device) return fail(RTA_E_INVALID_ARG, "the pipeline's device must be the current device");
+  uint8_t* base = nullptr;
+  s = noalloc_scratch(dev, &base);
+  if (s != RTA_OK) return s;
+  unsigned long long* queue = reinterpret_cast<unsigned long long*>(base + kScratchQueue);
+  uint32_t* status = reinterpret_cast<uint32_t*>(base + kScratchStatus);
+  const hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_scratch_reset, dim3(1), dim3(64), 0, st, queue, status);
+  RTA_HIP(hipGetLastError());
+  s = launch_batch(pipe, batch, tel_out, evt_out, queue, status, st);
+  if (s != RTA_OK) return s;
+  if (status_out) {
+    hipLaunchKernelGGL(k_status_copy, dim3(1), dim3(64), 0, st, (const uint32_t*)status, status_out);
+    RTA_HIP(hipGetLastError());
+  }
+  return RTA_OK;
 }
 
 rta_status rta_stereo(rta_pipeline* pipe, const int64_t* evt_tel_off, const int32_t* tel_type, int64_t n_evt,
@@ -674,7 +743,7 @@ rta_status rta_graph_capture(rta_pipeline* pipe, const rta_batch* batch, rta_hil
     delete g;
     return fail(RTA_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
   }
-  s = launch_batch(pipe, batch, tel_out, evt_out, pipe->capture_stream);
+  s = launch_batch(pipe, batch, tel_out, evt_out, pipe->d_queue, pipe->d_status, pipe->capture_stream);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(pipe->capture_stream, &graph);
   if (s != RTA_OK || e != hipSuccess) {
