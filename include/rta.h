@@ -410,6 +410,18 @@ rta_status rta_mlp_train_step(rta_mlp* m, const float* x, const float* label, co
 rta_status rta_mlp_train_step_rows(rta_mlp* m, const float* x, const float* label, const float* log10e,
                                    int64_t n_data, const int64_t* rows, int64_t B, float* loss, rta_stream stream);
 
+/* Inspection of the last loss_grad / train_step(_rows) pass of this network:
+ * copies the bfloat16 values that pass stored for the weight-gradient
+ * contraction.  which = 0: the standardised input (16 rows; rows 10..15 are
+ * zero); 1..3: the hidden activations h1..h3 (64 rows); 4..6: the gradient
+ * signals at the pre-activations of layers 1..3 (64 rows, the ReLU mask
+ * applied); 7: the gradient at the two outputs (16 rows; rows 2..15 zero).
+ * out: DEVICE uint16 (bfloat16 bits) [rows][B], feature-major, B = that
+ * pass's batch size (else RTA_E_SHAPE; RTA_E_INVALID_ARG before any pass).
+ * Asynchronous on the stream; read it before the network's next pass. */
+#define RTA_MLP_STORED_COUNT 8
+rta_status rta_mlp_stored(const rta_mlp* m, int32_t which, int64_t B, uint16_t* out, rta_stream stream);
+
 /* ------------------------------------------------------------------------
  * Classification with fallback.  Plain scaled-width / scaled-length box cuts
  * serve as the baseline and as the fallback when a telescope's features are

@@ -122,6 +122,29 @@ def backward(theta, cache, g_out, emulate_bf16=True):
     return pack(grads)
 
 
+def layer_sums(theta, layer, h_prev):
+    """One layer of the forward pass from given bf16-valued inputs h_prev
+    [B][fan_in]: the pre-activation a = h_prev @ bf16(W_l) + b_l (FP64) and
+    mag = |h_prev| @ |bf16(W_l)| + |b_l|, the sum of the absolute values of
+    its terms.  layer 1..4 (4: the output layer, whose a is the output)."""
+    p = unpack(theta)
+    W = bf16(p["W%d" % layer])
+    b = p["b%d" % layer]
+    h = np.asarray(h_prev, np.float64)
+    return h @ W + b, np.abs(h) @ np.abs(W) + np.abs(b)
+
+
+def backward_sums(theta, layer, g_next):
+    """The gradient that reaches the pre-activation of hidden layer l (1..3)
+    from bf16-valued gradients g_next [B][fan_out] of layer l+1, before the
+    ReLU mask: u = g_next @ bf16(W_{l+1})^T (FP64), and the sum of the
+    absolute values of its terms."""
+    p = unpack(theta)
+    W = bf16(p["W%d" % (layer + 1)])
+    g = np.asarray(g_next, np.float64)
+    return g @ W.T, np.abs(g) @ np.abs(W).T
+
+
 def loss_grad(theta, xs, label, log10e, emulate_bf16=True):
     out, cache = forward(theta, xs, emulate_bf16)
     L, g = loss_and_grad_out(out, label, log10e)

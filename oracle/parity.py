@@ -95,3 +95,36 @@ def stereo_mismatch(g_dir, o_dir, cond, c_max, tol=TOL):
     scale = (math.hypot(*o_dir) + c_max) * max(1.0, cond / 100.0)
     d = math.hypot(g_dir[0] - o_dir[0], g_dir[1] - o_dir[1])
     return d > tol * scale, d, tol * scale
+
+
+# ---------------------------------------------------------------------------
+# Network: float32 accumulation followed by bfloat16 rounding.
+#
+# A sum of n terms (products of bfloat16 values are exact in float32, and a
+# bias is one more term) evaluated in float32 in any order, with each
+# addition in error by at most one float32 ulp of its result (2^-23
+# relative: round-to-nearest or truncation), differs from its exact value by
+# at most n * 2^-23 * (sum of the absolute values of the terms), to first
+# order.  Whatever the kernels' order, their float32 result lies inside that
+# bracket, and after a monotone map (ReLU, or none) and rounding to bfloat16
+# inside the rounded bracket.  An element whose bracket holds one bfloat16
+# value must equal it exactly; one whose bracket straddles a rounding
+# boundary may take either side.
+ULP32 = 2.0 ** -23
+
+
+def bf16_bracket(exact, mag, n_terms, relu=False):
+    """(lo, hi) bfloat16 values (float64) that a float32 evaluation of the
+    sums ``exact`` (FP64) with term magnitudes ``mag`` can round to."""
+    from oracle.mlp import bf16
+    d = n_terms * ULP32 * np.asarray(mag, np.float64)
+    lo, hi = np.asarray(exact, np.float64) - d, np.asarray(exact, np.float64) + d
+    if relu:
+        lo, hi = np.maximum(lo, 0.0), np.maximum(hi, 0.0)
+    return bf16(lo), bf16(hi)
+
+
+def sum_bound(mag, n_terms):
+    """Largest |float32 evaluation - exact| of a sum of n_terms terms whose
+    absolute values add to ``mag``."""
+    return n_terms * ULP32 * np.asarray(mag, np.float64)

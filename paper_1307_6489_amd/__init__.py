@@ -157,6 +157,7 @@ SYMBOLS = {
     "rta_mlp_loss_grad": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp], ctypes.c_int),
     "rta_mlp_train_step": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_mlp_train_step_rows": ([_vp, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp], ctypes.c_int),
+    "rta_mlp_stored": ([_vp, _i32, _i64, _vp, _vp], ctypes.c_int),
     "rta_features": ([_vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_classify": ([_vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_pipeline_attach_mlp": ([_vp, _vp, _vp], ctypes.c_int),
@@ -164,6 +165,7 @@ SYMBOLS = {
 BOXCUT_MAX_BINS = 32
 MLP_N_PARAMS = 9154
 MLP_N_FEATURES = 10
+MLP_N_STORED = 8
 
 
 class BoxCutDesc(ctypes.Structure):
@@ -640,6 +642,18 @@ class Mlp:
         _check(lib().rta_mlp_loss_grad(self.handle, _ptr(x), _ptr(label), _ptr(log10e), B, _ptr(grad), _ptr(loss),
                                        _stream(stream)))
         return loss, grad
+
+    def stored(self, which, B, stream=None):
+        """rta_mlp_stored: the bfloat16 values (as float32, feature-major
+        [rows][B]) the last loss_grad / train_step pass stored; which 0..3:
+        input and hidden activations, 4..6: gradients at the pre-activations
+        of layers 1..3, 7: gradient at the outputs."""
+        import torch
+        rows = 16 if which in (0, 7) else 64
+        out = torch.empty((rows, B), dtype=torch.int16, device="cuda")
+        _check(lib().rta_mlp_stored(self.handle, which, B, _ptr(out), _stream(stream)))
+        bits = out.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+        return bits.view(np.float32)
 
     def train_step(self, x, label, log10e, loss_out=None, stream=None, rows=None):
         """One Adam step on the batch (x, label, log10e); with ``rows`` (int64

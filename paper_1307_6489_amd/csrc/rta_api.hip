@@ -51,6 +51,7 @@ struct rta_mlp {
   rta::MlpDev dev{};
   void* dmem = nullptr;
   int max_batch = 0, bpad_max = 0;
+  int64_t last_B = 0;  // batch of the last loss_grad / train_step pass (0: none yet)
   float lr = 1e-3f, beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
   int64_t step = 0;
   bool has_params = false;
@@ -937,6 +938,7 @@ static rta_status mlp_loss_grad(rta_mlp* m, const float* x, const float* label, 
   const int Bpad = (int)((B + 63) & ~63LL);
   RTA_HIP(rta::launch_mlp_rows_gather(m->dev, x, label, log10e, rows, n_data, (int)B, Bpad, nullptr, true, st));
   RTA_HIP(rta::launch_mlp_grad(m->dev, (int)B, Bpad, loss, st));
+  m->last_B = B;
   return RTA_OK;
 }
 
@@ -973,6 +975,20 @@ rta_status rta_mlp_train_step_rows(rta_mlp* m, const float* x, const float* labe
   rta_status s = mlp_loss_grad(m, x, label, log10e, rows, n_data, B, loss, (hipStream_t)stream);
   if (s != RTA_OK) return s;
   return mlp_adam(m, (hipStream_t)stream);
+}
+
+rta_status rta_mlp_stored(const rta_mlp* m, int32_t which, int64_t B, uint16_t* out, rta_stream stream) {
+  if (!m || !out) return fail(RTA_E_INVALID_ARG, "null network or output");
+  if (which < 0 || which >= RTA_MLP_STORED_COUNT) return fail(RTA_E_INVALID_ARG, "which must be in [0, 8)");
+  if (m->last_B == 0) return fail(RTA_E_INVALID_ARG, "no loss_grad / train_step pass yet");
+  if (B != m->last_B) return fail(RTA_E_SHAPE, "B must be the batch size of the last pass");
+  const uint16_t* src[RTA_MLP_STORED_COUNT] = {m->dev.H0, m->dev.H1, m->dev.H2, m->dev.H3,
+                                               m->dev.G1, m->dev.G2, m->dev.G3, m->dev.G4};
+  const size_t rows = (which == 0 || which == 7) ? 16 : 64;  // padded input / output width, hidden width
+  const size_t Bpad = (size_t)((B + 63) & ~63LL);
+  RTA_HIP(hipMemcpy2DAsync(out, (size_t)B * 2, src[which], Bpad * 2, (size_t)B * 2, rows, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+  return RTA_OK;
 }
 
 }  // extern "C"

@@ -64,7 +64,7 @@ def test_features_parity(dev, small_model):
 ULP32 = 2.0 ** -23
 
 
-def knife_edge(bc, feat, score=None):
+def knife_edge(bc, feat, score=None, score_tol=1e-3):
     """Rows whose float32 inputs lie within a few float32 ulps of a decision
     edge (log10 size is computed by each side's own log10 and may differ by
     one ulp)."""
@@ -77,7 +77,7 @@ def knife_edge(bc, feat, score=None):
     near_bin = obox.bin_edge_distance(bc, lgs) < 4 * ULP32 * (np.abs(lgs) + 1.0)
     edge = near_range | near_bin
     if score is not None:
-        edge |= np.abs(score - bc.mlp_cut) < 1e-3
+        edge |= np.abs(score - bc.mlp_cut) < score_tol
     return edge
 
 
@@ -96,26 +96,37 @@ def test_classify_parity_box_only(dev, small_model):
 
 
 def test_classify_parity_with_network(dev, small_model):
+    """rta_classify with the network against the oracle's decision rule
+    applied to the GPU's own features and network outputs, element by
+    element: fallback and gamma decisions exact, network scores within 1e-5
+    relative (float32 sigmoid), energies equal to the network's output, the
+    box-cut rows' scores exact and energies within 1e-5.  The features are
+    compared with the oracle's in test_features_parity, the network outputs
+    layer by layer in test_gpu_mlp; only rows whose inputs sit within float32
+    rounding of a range, bin or score edge are skipped, at most 1 %."""
     import torch
     cam, tr, te, net, bc, info = small_model
     rec = te["rec"]
-    out = rta.classify(net, bc, rec_tensor(rec, dev)).cpu().numpy()
-    feat = omlp.features_from_records(rec).astype(np.float32)
-    params = net.get_params().astype(np.float64)
-    ok_x = np.all(np.isfinite(feat), 1)
-    mean = tr["x"][learn.usable(tr["x"], tr["rec"])].mean(0)
-    std = tr["x"][learn.usable(tr["x"], tr["rec"])].std(0) + 1e-6
-    xs = np.zeros_like(feat, dtype=np.float64)
-    xs[ok_x] = ((feat[ok_x] - mean.astype(np.float32)) / std.astype(np.float32)).astype(np.float32)
-    o, _ = omlp.forward(params, xs)
+    R = rec_tensor(rec, dev)
+    out = rta.classify(net, bc, R).cpu().numpy().astype(np.float64)
+    xg = rta.features(R)
+    fin = torch.isfinite(xg).all(1)
+    o = np.full((len(rec), 2), np.nan)
+    o[fin.cpu().numpy()] = net.forward(xg[fin].contiguous()).cpu().numpy()
+    feat = xg.cpu().numpy()
     s, e, g, fb = obox.classify(bc, feat, o[:, 0], o[:, 1])
-    ok = ~knife_edge(bc, feat, s)
-    assert ok.mean() > 0.98
+    ok = ~knife_edge(bc, feat, s, score_tol=1e-6)
+    assert ok.mean() > 0.99
     assert np.array_equal(out[ok, 3].astype(np.int64), fb[ok])
     assert np.array_equal(out[ok, 2].astype(np.int64), g[ok])
     net_rows = ok & (fb == 0)
-    assert net_rows.sum() > 1000
-    assert np.sqrt(np.mean((out[net_rows, 0] - s[net_rows]) ** 2)) < 1e-3
+    box_rows = ok & (fb == 1)
+    assert net_rows.sum() > 1000 and box_rows.sum() > 10
+    assert np.all(np.abs(out[net_rows, 0] - s[net_rows]) <= 1e-5 * s[net_rows] + 1e-7)
+    assert np.array_equal(out[net_rows, 1], o[net_rows, 1].astype(np.float32).astype(np.float64))
+    assert np.array_equal(out[box_rows, 0], s[box_rows])
+    fe = box_rows & np.isfinite(e)
+    assert np.all(np.abs(out[fe, 1] - e[fe]) <= 1e-5 * (np.abs(e[fe]) + 1.0))
 
 
 def test_event_pass_with_network(dev, small_model):

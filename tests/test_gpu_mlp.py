@@ -1,20 +1,32 @@
 """GPU parity of the BF16-MFMA network kernels against the oracle with
-bfloat16 rounding emulated at the same storage points.
+bfloat16 rounding emulated at the same storage points, element by element.
 
-Tolerance.  bf16 x bf16 products are exact in FP32, so a single contraction
-differs from the FP64 oracle only by FP32 accumulation rounding.  Across
-layers that rounding can flip the bf16 rounding of an activation or gradient
-(probability ~1e-4 per element), which moves a few rows by ~2^-8 relative.
-Hence: relative Frobenius error <= 1e-3 for outputs and gradients, and most
-rows agreeing to 1e-5.
+Every contraction is checked on its own, from the values the kernels stored at
+the bfloat16 storage points of the same pass (rta_mlp_stored): each layer's
+stored activations and gradient signals must equal the oracle's bfloat16
+rounding of that layer computed exactly from the kernels' own inputs to the
+layer, except elements whose exact value lies within the float32
+accumulation bound (n terms x 2^-23 x the sum of the terms' magnitudes) of a
+bfloat16 rounding boundary, which may take either neighbour; the share of such
+elements is asserted.  FP32 results (outputs, weight gradients, loss) must lie
+within that bound of their exact values element by element.  Rows whose
+forward chain met no such boundary must equal the oracle's forward from the
+raw inputs exactly at every storage point.
 """
 import numpy as np
 import pytest
 
+import oracle.parity as par
 import paper_1307_6489_amd as rta
 from oracle import mlp
 
 pytestmark = pytest.mark.gpu
+
+GRAD_SPLIT = 16   # batch slices the weight-gradient kernel adds in order
+# largest share of bracketed (two-valued) elements per hidden layer; the
+# float32 accumulation bound over 64 terms covers about 2.5 % of the bf16
+# rounding boundaries at these weight scales, 11 terms about 0.3 %
+MAX_BRACKETED = {1: 0.01, 2: 0.06, 3: 0.06}
 
 
 def say(*a):
@@ -35,10 +47,6 @@ def t(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
 
 
-def rel_fro(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
-
-
 def make(dev, seed, B, scale=1.0):
     rng = np.random.default_rng(seed)
     theta = (mlp.init_params(seed) * scale).astype(np.float32)
@@ -50,15 +58,59 @@ def make(dev, seed, B, scale=1.0):
     return net, theta.astype(np.float64), x, lab, y
 
 
+def in_bracket(gpu, lo, hi, what):
+    """Every element inside its bracket; returns the bracketed (two-valued) mask."""
+    inside = (gpu >= lo) & (gpu <= hi)
+    if not inside.all():
+        bad = np.argwhere(~inside)[:5]
+        raise AssertionError("%s: %d elements outside the bracket, first %s: gpu %s, allowed [%s, %s]"
+                             % (what, int((~inside).sum()), bad.tolist(), gpu[tuple(bad.T)], lo[tuple(bad.T)],
+                                hi[tuple(bad.T)]))
+    return lo != hi
+
+
+def stored(net, B):
+    """Activations H0..H3 and gradient signals G1..G4 of the last pass, [B][F]."""
+    S = [net.stored(k, B).T.astype(np.float64) for k in range(rta.MLP_N_STORED)]
+    H = [S[0][:, :10], S[1], S[2], S[3]]
+    G = {1: S[4], 2: S[5], 3: S[6], 4: S[7][:, :2]}
+    assert not np.any(S[0][:, 10:]) and not np.any(S[7][:, 2:])
+    return H, G
+
+
+def check_forward(net, theta, xs32, out, H, tag):
+    """Input rounding, the three hidden layers and the output layer against
+    the oracle from the kernels' own layer inputs; returns the rows whose
+    chain met no rounding boundary."""
+    assert np.array_equal(H[0], mlp.bf16(xs32)), tag + ": standardised input"
+    B = xs32.shape[0]
+    clean = np.ones(B, bool)
+    for l in (1, 2, 3):
+        a, mag = mlp.layer_sums(theta, l, H[l - 1])
+        lo, hi = par.bf16_bracket(a, mag, H[l - 1].shape[1] + 1, relu=True)
+        br = in_bracket(H[l], lo, hi, "%s: h%d" % (tag, l))
+        assert br.mean() <= MAX_BRACKETED[l], (tag, l, br.mean())
+        clean &= ~br.any(1)
+    a, mag = mlp.layer_sums(theta, 4, H[3])
+    assert np.all(np.abs(out - a) <= par.sum_bound(mag, 65)), tag + ": output layer"
+    # rows without a boundary in their chain: the oracle's forward from the raw input, exactly
+    ref, cache = mlp.forward(theta, xs32.astype(np.float64))
+    for l in (1, 2, 3):
+        assert np.array_equal(H[l][clean], cache["h"][l][clean]), (tag, l)
+    assert np.all(np.abs(out[clean] - ref[clean]) <= par.sum_bound(mag[clean], 65)), tag + ": end to end"
+    return clean
+
+
 @pytest.mark.parametrize("B", [1, 37, 1000, 4096])
 def test_forward_parity(dev, B):
     say("forward parity B=%d seed 5" % B)
     net, theta, x, lab, y = make(dev, 5, B)
-    out = net.forward(t(x, dev)).cpu().numpy()
-    ref, _ = mlp.forward(theta, x.astype(np.float64))
-    assert rel_fro(out, ref) <= 1e-3
-    close = np.all(np.abs(out - ref) <= 1e-5 * (np.abs(ref) + 1.0), axis=1)
-    assert close.mean() >= 0.8
+    X = t(x, dev)
+    net.loss_grad(X, t(lab, dev), t(y, dev))     # a pass that stores its activations
+    H, _ = stored(net, B)
+    out = net.forward(X).cpu().numpy().astype(np.float64)
+    clean = check_forward(net, theta, x, out, H, "B=%d" % B)
+    say("  rows with no rounding boundary in their chain: %d of %d" % (clean.sum(), B))
 
 
 def test_standardisation_inside_kernel(dev):
@@ -66,29 +118,64 @@ def test_standardisation_inside_kernel(dev):
     theta = mlp.init_params(9).astype(np.float32)
     mean = rng.normal(size=10).astype(np.float32) * 5
     std = rng.uniform(0.5, 3, size=10).astype(np.float32)
-    x = (rng.normal(size=(300, 10)) * std + mean).astype(np.float32)
-    net = rta.Mlp(max_batch=64)
+    B = 300
+    x = (rng.normal(size=(B, 10)) * std + mean).astype(np.float32)
+    net = rta.Mlp(max_batch=512)
     net.set_params(theta, mean, std)
-    out = net.forward(t(x, dev)).cpu().numpy()
+    X = t(x, dev)
+    net.loss_grad(X, t(np.zeros(B), dev), t(np.zeros(B), dev))
+    H, _ = stored(net, B)
+    out = net.forward(X).cpu().numpy().astype(np.float64)
     xs = ((x - mean) / std).astype(np.float32)   # the kernels standardise in FP32
-    ref, _ = mlp.forward(theta.astype(np.float64), xs.astype(np.float64))
-    assert rel_fro(out, ref) <= 1e-3
+    check_forward(net, theta.astype(np.float64), xs, out, H, "standardised")
 
 
 @pytest.mark.parametrize("B", [64, 1000, 4096])
 def test_gradient_parity(dev, B):
     say("gradient parity B=%d seed 6" % B)
     net, theta, x, lab, y = make(dev, 6, B)
-    loss, grad = net.loss_grad(t(x, dev), t(lab, dev), t(y, dev))
-    L_ref, g_ref = mlp.loss_grad(theta, x.astype(np.float64), lab, y)
-    assert float(loss.cpu()[0]) == pytest.approx(L_ref, rel=1e-4)
-    g = grad.cpu().numpy().astype(np.float64)
-    assert rel_fro(g, g_ref) <= 1e-3
-    off = 0
-    for name, shp in mlp.SHAPES:
-        n = int(np.prod(shp))
-        assert rel_fro(g[off:off + n], g_ref[off:off + n]) <= 5e-3, name
-        off += n
+    X, Lb, Y = t(x, dev), t(lab, dev), t(y, dev)
+    loss, grad = net.loss_grad(X, Lb, Y)
+    H, G = stored(net, B)
+    out = net.forward(X).cpu().numpy().astype(np.float64)
+    check_forward(net, theta, x, out, H, "B=%d" % B)
+    lab64, y64 = lab.astype(np.float64), y.astype(np.float64)
+    z, e = out[:, 0], out[:, 1]
+    # output gradient: float32 sigmoid (exp, add, divide), subtraction, division by B
+    _, g = mlp.loss_and_grad_out(out, lab64, y64)
+    sig = 1.0 / (1.0 + np.exp(-z))
+    m = (lab64 > 0.5).astype(np.float64)
+    d = np.stack([8 * par.ULP32 * (np.abs(sig) + lab64) / B,
+                  8 * par.ULP32 * m * (np.abs(e) + np.abs(y64)) / B], 1)
+    in_bracket(G[4], mlp.bf16(g - d), mlp.bf16(g + d), "output gradient")
+    # gradient signals of the hidden layers from the kernels' own next-layer signals
+    for l in (3, 2, 1):
+        u, mag = mlp.backward_sums(theta, l, G[l + 1])
+        live = H[l] > 0
+        lo, hi = par.bf16_bracket(u * live, mag * live, 16 if l == 3 else 64)
+        br = in_bracket(G[l], lo, hi, "g%d" % l)
+        assert br.mean() <= MAX_BRACKETED[2], (l, br.mean())
+    # weight and bias gradients: batch contractions of the stored values
+    exact, bound = {}, {}
+    for l in (1, 2, 3, 4):
+        exact["W%d" % l] = H[l - 1].T @ G[l]
+        bound["W%d" % l] = par.sum_bound(np.abs(H[l - 1]).T @ np.abs(G[l]), B + GRAD_SPLIT)
+        exact["b%d" % l] = G[l].sum(0)
+        bound["b%d" % l] = par.sum_bound(np.abs(G[l]).sum(0), B + GRAD_SPLIT)
+    gg = grad.cpu().numpy().astype(np.float64)
+    ex, bd = mlp.pack(exact), mlp.pack(bound)
+    bad = np.abs(gg - ex) > bd
+    assert not bad.any(), ("weight gradient", np.argwhere(bad)[:5].ravel(), gg[bad][:5], ex[bad][:5])
+    # loss: float32 per-row terms summed over the batch
+    bce = np.maximum(z, 0) - z * lab64 + np.log1p(np.exp(-np.abs(z)))
+    row = bce + m * (e - y64) ** 2
+    mag = np.maximum(z, 0) + np.abs(z * lab64) + np.log1p(np.exp(-np.abs(z))) + m * (e - y64) ** 2
+    L = float(loss.cpu()[0])
+    assert abs(L - row.sum() / B) <= par.sum_bound(mag.sum(), B + 72) / B
+    # the gradient from the oracle's pass on the raw inputs (its own rounding choices): close overall
+    _, g_ref = mlp.loss_grad(theta, x.astype(np.float64), lab, y)
+    worst = np.abs(gg - g_ref) / (np.abs(g_ref) + 1e-3 * np.abs(g_ref).max())
+    say("  largest relative difference to the oracle's own pass: %.2e" % worst.max())
 
 
 def test_adam_step_parity(dev):

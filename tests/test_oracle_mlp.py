@@ -128,3 +128,94 @@ def test_features_from_records_log_size_edges():
     assert x[2, 0] == -math.inf
     assert math.isnan(x[3, 0]) and math.isnan(x[4, 0])
     assert np.all(x[:, 1] == 0.1)
+
+
+def test_layer_sums_hand_case():
+    """Layer 2 with two inputs and hand-set weights: the pre-activation and
+    the magnitude sum written out (weights already bfloat16 values)."""
+    p = {k: np.zeros(s) for k, s in mlp.SHAPES}
+    p["W2"][0, 0], p["W2"][1, 0], p["b2"][0] = 0.5, -2.0, 0.25
+    p["W2"][0, 3], p["b2"][3] = 3.0, -1.0
+    theta = mlp.pack(p)
+    h = np.zeros((2, 64))
+    h[0, :2] = [1.0, 0.75]
+    h[1, :2] = [4.0, 0.0]
+    a, mag = mlp.layer_sums(theta, 2, h)
+    assert a[0, 0] == 0.5 * 1.0 - 2.0 * 0.75 + 0.25 and mag[0, 0] == 0.5 + 1.5 + 0.25
+    assert a[1, 0] == 2.0 + 0.25 and mag[1, 0] == 2.25
+    assert a[0, 3] == 3.0 - 1.0 and mag[0, 3] == 4.0
+    assert a[1, 3] == 12.0 - 1.0 and mag[1, 3] == 13.0
+    assert not np.any(a[:, [1, 2]]) and not np.any(mag[:, 4:])
+    # the weights enter rounded to bfloat16: 0.1 becomes 0x3DCD
+    p["W2"][0, 5] = 0.1
+    a, _ = mlp.layer_sums(mlp.pack(p), 2, h)
+    assert a[1, 5] == 4.0 * 0.10009765625
+
+
+def test_backward_sums_hand_case():
+    """Gradient reaching hidden layer 3 from the two outputs: u = g4 W4^T."""
+    p = {k: np.zeros(s) for k, s in mlp.SHAPES}
+    p["W4"][7, 0], p["W4"][7, 1], p["W4"][9, 1] = 2.0, -0.5, 4.0
+    g = np.array([[1.0, 2.0], [-3.0, 0.5]])
+    u, mag = mlp.backward_sums(mlp.pack(p), 3, g)
+    assert u[0, 7] == 2.0 - 1.0 and mag[0, 7] == 3.0
+    assert u[1, 7] == -6.0 - 0.25 and mag[1, 7] == 6.25
+    assert u[0, 9] == 8.0 and u[1, 9] == 2.0
+    assert np.count_nonzero(u) == 4
+
+
+def test_layer_sums_reproduce_the_pinned_pass():
+    """Rounding each layer_sums result to bfloat16 after the ReLU, and the
+    masked backward_sums, walk exactly through forward / backward (whose
+    results are pinned above by the closed form and finite differences)."""
+    rng = np.random.default_rng(4)
+    theta = mlp.init_params(4)
+    x = rng.normal(size=(50, 10))
+    out, cache = mlp.forward(theta, x)
+    h = mlp.bf16(x.astype(np.float32))
+    for l in (1, 2, 3):
+        a, mag = mlp.layer_sums(theta, l, h)
+        assert np.all(mag >= np.abs(a))
+        h = mlp.bf16(np.maximum(a, 0.0))
+        assert np.array_equal(h, cache["h"][l])
+    a, _ = mlp.layer_sums(theta, 4, h)
+    assert np.array_equal(a, out)
+    lab = (rng.random(50) < 0.5).astype(np.float64)
+    y = rng.normal(size=50)
+    _, g_out = mlp.loss_and_grad_out(out, lab, y)
+    grads = mlp.unpack(mlp.backward(theta, cache, g_out))
+    g = mlp.bf16(g_out)
+    for l in (3, 2, 1):
+        u, _ = mlp.backward_sums(theta, l, g)
+        g = mlp.bf16(u * (cache["h"][l] > 0))
+        assert np.allclose(grads["W%d" % l], cache["h"][l - 1].T @ g, rtol=1e-12, atol=0)
+
+
+def test_bf16_bracket_holds_float32_sums_in_any_order():
+    """Sums of 65 bfloat16 products plus a bias, added in float32 in random
+    orders (and with truncation instead of rounding after every addition):
+    the rounded result always lies in the bracket, and the bracket is a
+    single value when the exact sum is far from a rounding boundary."""
+    import oracle.parity as par
+    rng = np.random.default_rng(17)
+    n_rows, K = 400, 64
+    h = mlp.bf16(np.abs(rng.normal(size=(n_rows, K))))
+    w = mlp.bf16(rng.normal(size=(n_rows, K)) * 0.2)
+    b = rng.normal(size=n_rows).astype(np.float32).astype(np.float64)
+    terms = np.concatenate([h * w, b[:, None]], 1)          # products are exact in float32
+    exact = terms.sum(1)
+    mag = np.abs(terms).sum(1)
+    lo, hi = par.bf16_bracket(exact, mag, K + 1, relu=True)
+    assert np.all(lo <= hi)
+    for trial in range(20):
+        perm = rng.permutation(K + 1)
+        acc = np.zeros(n_rows, np.float32)
+        for k in perm:
+            s = acc + terms[:, k].astype(np.float32)
+            if trial % 2:       # truncate toward zero instead of rounding
+                s64 = acc.astype(np.float64) + terms[:, k]
+                s = np.where(np.abs(s.astype(np.float64)) > np.abs(s64), np.nextafter(s, np.float32(0)), s)
+            acc = s.astype(np.float32)
+        got = mlp.bf16(np.maximum(acc, 0))
+        assert np.all((got >= lo) & (got <= hi)), trial
+    assert np.mean(lo == hi) > 0.9
