@@ -106,34 +106,97 @@ def cpu_baseline(pool, ty, off, target_s=10.0, single_s=3.0):
             "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
-def latency_run(args, dev):
-    """Array events with the 2048 x 128 dual-gain type dominating (1:1:8),
-    stereo and the gamma/hadron network attached, fed from page-locked host
-    memory at a paced rate; per-chunk arrival -> event-record latency."""
-    import torch
+def cpu_baseline_c0(threads):
+    """The oracle on the whole plain parity set: 1000 single-gain events of
+    the 1855-pixel camera, 30 samples (seed 0), with all threads and with one."""
     import dl0sim
-    import dl0sim.workloads as W
-    import paper_1307_6489_amd as rta
+    import oracle
+    ct = dl0sim.camera_c0()
+    _, tr = dl0sim.plain_events(ct, 0, 1000)
+    oc = oracle.Camera.from_type(ct)
+    E = len(tr)
+    ty = np.zeros(E, np.int32)
+    off = np.arange(E, dtype=np.int64) * oc.event_elems
+    res = {"events": E, "workload": "1855 px x 30 samples, single gain, 1000 events, seed 0"}
+    for name, n_thr in (("threads", threads), ("single_thread", 1)):
+        t0 = time.perf_counter()
+        oracle.reconstruct_batch([oc], ty, tr.reshape(-1), off, n_threads=n_thr)
+        dt = time.perf_counter() - t0
+        res[name] = {"cores": n_thr, "camera_events_per_s": E / dt, "seconds": dt,
+                     "input_GBps": E * ct.dl0_bytes / dt / 1e9}
+    return res
+
+
+def cpu_baseline_c2(arr, threads, n_evt=2000):
+    """The oracle on the first ``n_evt`` array events of the batched job:
+    Hillas per telescope (all threads) and stereo per array event."""
+    import oracle
+    aw, eo, ty, off = arr
+    cams = aw.pool.cams
+    ocs = [oracle.Camera.from_type(c) for c in cams]
+    n_tel = int(eo[n_evt])
+    focal = np.array([c.focal_m for c in cams])
+    t0 = time.perf_counter()
+    rec = oracle.reconstruct_batch(ocs, ty[:n_tel], aw.pool.blob, off[:n_tel], n_threads=threads)
+    t1 = time.perf_counter()
+    for e in range(n_evt):
+        r = rec[eo[e]:eo[e + 1]]
+        valid = ((r["flags"] & 1) == 0).astype(np.int32)
+        oracle.stereo(r["size"], r["cog_x"], r["cog_y"], r["length"], r["width"], r["psi"], valid,
+                      focal[ty[eo[e]:eo[e + 1]]])
+    t2 = time.perf_counter()
+    dl0 = np.array([c.dl0_bytes for c in cams], np.int64)
+    return {"array_events": n_evt, "telescopes": n_tel, "cores": threads, "seconds": t2 - t0,
+            "stereo_seconds": t2 - t1, "array_events_per_s": n_evt / (t2 - t0),
+            "camera_events_per_s": n_tel / (t2 - t0), "input_GBps": float(dl0[ty[:n_tel]].sum()) / (t2 - t0) / 1e9,
+            "workload": "first %d array events of the batched job (multiplicity 2..40, 1:3:6 types)" % n_evt}
+
+
+def train_network(dev):
+    """A gamma/hadron + energy network for the runs with classification:
+    2 epochs on 30k generated images of the 1855-pixel camera (seed 3)."""
+    import dl0sim
     from paper_1307_6489_amd import learn
-    from paper_1307_6489_amd import stream as st
-    t0 = time.time()
     tr = learn.image_features(dl0sim.camera_c0(), 30_000, 3, dev)
     net, bc, info = learn.train(tr, dev, epochs=2, batch=1024, lr=2e-3)
-    aw = W.array_events(args.latency_events, seed=5, weights=(1.0, 1.0, 8.0))
+    return net, bc
+
+
+def latency_run(args, dev, network):
+    """Array events with the 2048 x 128 dual-gain type dominating (1:1:8),
+    stereo and the gamma/hadron network attached, fed from page-locked host
+    memory at a paced rate, cycling through a rendered pool of array events
+    until at least --latency-events array events are timed; per-array-event
+    latency from device clocks (record write minus the chunk's copy
+    completion, and minus the chunk's arrival on the host clock)."""
+    import dl0sim.workloads as W
+    import paper_1307_6489_amd as rta
+    from paper_1307_6489_amd import stream as st
+    t0 = time.time()
+    net, bc = network
+    aw = W.array_events(args.latency_pool, seed=5, weights=(1.0, 1.0, 8.0))
     ps = st.PinnedArrayStream(aw, 8 << 20)
     cams = [rta.Camera.from_type(c) for c in aw.pool.cams]
     pipe = rta.Pipeline(cams, do_stereo=True)
     pipe.set_schedule(*args.latency_schedule)
     pipe.attach_mlp(net, bc)
-    n_chunks = min(len(ps.chunks), 600)
-    r = st.paced_latency(pipe, ps, args.rate, n_chunks, dev)
-    r["telescopes"] = int(len(aw.tel_type))
+    warmup = 4
+    per = np.array([c[3] - c[2] for c in ps.chunks], np.int64)
+    n_chunks, got = 0, 0
+    while got < args.latency_events:
+        got += int(per[(warmup + n_chunks) % len(per)])
+        n_chunks += 1
+    r = st.paced_latency(pipe, ps, args.rate, n_chunks, dev, warmup=warmup)
+    if pipe.status():
+        raise RuntimeError("device status word %#x in the latency run" % pipe.status())
+    r["pool_array_events"] = args.latency_pool
+    r["pool_telescopes"] = int(len(aw.tel_type))
     r["mix"] = "1855x40 : 1764x25 : 2048x128 = 1:1:8, multiplicity 2..40, network + box-cut fallback attached"
     log("latency run: %s (%.1f s)" % (r, time.time() - t0))
     return r
 
 
-def array_batch_run(args, dev, stream):
+def array_batch_run(args, dev, stream, network):
     """Batched array events: ragged array events of multiplicity 2..40 over
     the three camera types (1:3:6), replicated from a device-resident pool of
     rendered array events, through one graph-replayed rta_process_batch with
@@ -172,6 +235,23 @@ def array_batch_run(args, dev, stream):
     if status:
         raise RuntimeError("device status word %#x" % status)
     ms = a.elapsed_time(z) / args.array_steps
+    # the same job with the network attached: classification in the per-event pass
+    net_ms = None
+    if network is not None:
+        pipe.attach_mlp(*network)
+        with torch.cuda.stream(stream):
+            g2 = pipe.capture(b, tel, evt)
+            g2.launch(stream)
+            stream.synchronize()
+            a.record(stream)
+            for _ in range(args.array_steps):
+                g2.launch(stream)
+            z.record(stream)
+            stream.synchronize()
+        net_ms = a.elapsed_time(z) / args.array_steps
+        if pipe.status():
+            raise RuntimeError("device status word %#x with the network" % pipe.status())
+        del g2
     dl0 = np.array([c.dl0_bytes for c in aw.pool.cams], np.int64)
     ev = rta.records(evt, rta.EVENT_DTYPE)
     n_evt, n_tel = args.array_events, len(ty)
@@ -181,10 +261,14 @@ def array_batch_run(args, dev, stream):
          "stereo_valid_fraction": float(np.mean((ev["flags"] & rta.EVT_STEREO_INVALID) == 0)),
          "pool_array_events": args.array_pool, "pool_GB": aw.pool.blob.nbytes / 1e9,
          "schedule": list(best), "steps": args.array_steps, "graph": True}
+    if net_ms is not None:
+        r["with_network"] = {"gpu_ms_per_step": net_ms, "array_events_per_s": n_evt / (net_ms * 1e-3),
+                             "classification_ms_per_step": net_ms - ms,
+                             "classification_ns_per_array_event": (net_ms - ms) * 1e6 / n_evt}
     log("array batch: %s (%.1f s)" % (r, time.time() - t0))
     del graph, blob_d, b, tel, evt, tb
     torch.cuda.empty_cache()
-    return r
+    return r, (aw, eo, ty, off)
 
 
 def main():
@@ -206,9 +290,11 @@ def main():
     ap.add_argument("--stream-chunks", type=int, default=24,
                     help="also stream this many pinned-host chunks of 4 GB through the pipeline (0: skip); "
                          "reported as the PCIe-inclusive rate, never as value")
-    ap.add_argument("--latency-events", type=int, default=400,
-                    help="array events (1:1:8 mix, network attached) paced from pinned host at --rate GB/s "
+    ap.add_argument("--latency-events", type=int, default=5000,
+                    help="array events timed (1:1:8 mix, network attached) paced from pinned host at --rate GB/s "
                          "for per-event latency (0: skip)")
+    ap.add_argument("--latency-pool", type=int, default=400,
+                    help="rendered array events of the page-locked pool the paced run cycles through")
     ap.add_argument("--rate", type=float, default=8.0, help="paced DL0 rate for the latency run, GB/s")
     ap.add_argument("--array-events", type=int, default=200_000,
                     help="array events per step of the batched array-event run with stereo (0: skip)")
@@ -348,11 +434,13 @@ def main():
         out["pinned_stream"] = r
         log("pinned stream: %s (%.1f s)" % (r, time.time() - t0))
         del pinned
+    network = train_network(dev) if (args.array_events > 0 or args.latency_events > 0) else None
+    arr = None
     if args.array_events > 0:
-        out["array_batch"] = array_batch_run(args, dev, stream)
+        out["array_batch"], arr = array_batch_run(args, dev, stream, network)
     if args.latency_events > 0:
         args.latency_schedule = pipe.schedule()
-        out["array_latency"] = latency_run(args, dev)
+        out["array_latency"] = latency_run(args, dev, network)
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -361,7 +449,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(pool, ty, off)
+        cb = cpu_baseline(pool, ty, off)
+        cb["c0_parity_set"] = cpu_baseline_c0(cb["cores"])
+        if arr is not None:
+            cb["c2_array_events"] = cpu_baseline_c2(arr, cb["cores"])
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

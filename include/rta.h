@@ -176,6 +176,8 @@ typedef struct rta_batch {
   const int64_t* tel_trace_off; /* [n_tel] element offset of the telescope's trace block (multiple of 8) */
   int64_t n_evt;
   int64_t n_tel;
+  uint64_t* evt_done_clock;     /* NULLABLE [n_evt]: with do_stereo, the device clock (see
+                                   rta_device_clock_hz) at which each event record was written */
 } rta_batch;
 
 typedef struct rta_pipeline_params {
@@ -204,6 +206,13 @@ const char* rta_last_error(void);
 int32_t rta_version(void);
 /* Number of compute units of the current device (for schedules). */
 rta_status rta_device_cus(int32_t* n_cu);
+/* Rate of the device clock that rta_device_stamp and rta_batch.evt_done_clock
+ * read (a constant-rate counter, independent of the shader clock), in Hz. */
+rta_status rta_device_clock_hz(int64_t* hz);
+/* Writes the device clock to *slot (DEVICE uint64) when the stream reaches
+ * this point: stamps the completion of earlier work on that stream (for
+ * example a host-to-device copy) on the clock of evt_done_clock. */
+rta_status rta_device_stamp(uint64_t* slot, rta_stream stream);
 
 /* Create / destroy a camera type.  Quantises pedestals to Q8 and builds the
  * integer cleaning thresholds and neighbour tables on the current device.

@@ -65,7 +65,7 @@ class CameraInfo(ctypes.Structure):
 class Batch(ctypes.Structure):
     _fields_ = [("traces", ctypes.c_void_p), ("traces_len", ctypes.c_int64), ("evt_tel_off", ctypes.c_void_p),
                 ("tel_type", ctypes.c_void_p), ("tel_trace_off", ctypes.c_void_p), ("n_evt", ctypes.c_int64),
-                ("n_tel", ctypes.c_int64)]
+                ("n_tel", ctypes.c_int64), ("evt_done_clock", ctypes.c_void_p)]
 
 
 class PipelineParams(ctypes.Structure):
@@ -121,6 +121,8 @@ SYMBOLS = {
     "rta_last_error": ([], ctypes.c_char_p),
     "rta_version": ([], _i32),
     "rta_device_cus": ([_vp], ctypes.c_int),
+    "rta_device_clock_hz": ([_vp], ctypes.c_int),
+    "rta_device_stamp": ([_vp, _vp], ctypes.c_int),
     "rta_camera_create": ([_vp, _vp], ctypes.c_int),
     "rta_camera_destroy": ([_vp], ctypes.c_int),
     "rta_camera_get_info": ([_vp, _vp], ctypes.c_int),
@@ -235,6 +237,23 @@ def device_cus():
     n = ctypes.c_int32()
     _check(lib().rta_device_cus(ctypes.byref(n)))
     return n.value
+
+
+def device_clock_hz():
+    """Rate of the device clock of device_stamp / evt_done_clock, Hz."""
+    v = ctypes.c_int64()
+    _check(lib().rta_device_clock_hz(ctypes.byref(v)))
+    return v.value
+
+
+def device_stamp(slot, stream=None):
+    """Write the device clock into ``slot`` (int64 device tensor, one element)
+    when ``stream`` reaches this point."""
+    import torch
+    _require(slot, torch.int64, name="slot")
+    if slot.numel() < 1:
+        raise ValueError("slot must hold one element")
+    _check(lib().rta_device_stamp(_ptr(slot), _stream(stream)))
 
 
 def list_schedules():
@@ -372,7 +391,9 @@ class Pipeline:
         return s.as_tuple()
 
     @staticmethod
-    def make_batch(traces, tel_type, tel_trace_off, evt_tel_off=None):
+    def make_batch(traces, tel_type, tel_trace_off, evt_tel_off=None, evt_done_clock=None):
+        """evt_done_clock: optional int64 device tensor [n_evt] that receives the
+        device clock at each event record's write."""
         import torch
         _require(traces, torch.uint16, name="traces")
         _require(tel_type, torch.int32, name="tel_type")
@@ -384,8 +405,11 @@ class Pipeline:
         if evt_tel_off is not None:
             _require(evt_tel_off, torch.int64, name="evt_tel_off")
             n_evt = evt_tel_off.numel() - 1
-        b = Batch(_ptr(traces), traces.numel(), _ptr(evt_tel_off), _ptr(tel_type), _ptr(tel_trace_off), n_evt, n_tel)
-        b._keep = (traces, tel_type, tel_trace_off, evt_tel_off)
+        if evt_done_clock is not None:
+            _require(evt_done_clock, torch.int64, (n_evt,), "evt_done_clock")
+        b = Batch(_ptr(traces), traces.numel(), _ptr(evt_tel_off), _ptr(tel_type), _ptr(tel_trace_off), n_evt, n_tel,
+                  _ptr(evt_done_clock))
+        b._keep = (traces, tel_type, tel_trace_off, evt_tel_off, evt_done_clock)
         return b
 
     def alloc_outputs(self, batch, device):

@@ -1211,6 +1211,7 @@ __global__ __launch_bounds__(kEvtNT) void k_event(EventArgs a) {
       r.n_used = 0;
       r.flags = RTA_EVT_STEREO_INVALID | RTA_EVT_NO_MLP;
       a.out[e] = r;
+      if (a.done_clock) a.done_clock[e] = wall_clock64();
       atomicOr(a.status, RTA_STATUS_BAD_EVENT);
     }
     return;
@@ -1298,7 +1299,12 @@ __global__ __launch_bounds__(kEvtNT) void k_event(EventArgs a) {
       r.log10_energy = c[1] / c[2];
     }
     a.out[e] = r;
+    if (a.done_clock) a.done_clock[e] = wall_clock64();
   }
+}
+
+__global__ void k_stamp(uint64_t* slot) {
+  if (threadIdx.x == 0) *slot = wall_clock64();
 }
 
 // Network inputs of records, one thread per record.
@@ -1492,6 +1498,11 @@ hipError_t launch_classify(const MlpDev& w, bool have_mlp, const rta_boxcut_desc
   const int64_t tiles = (n + 15) / 16;
   hipLaunchKernelGGL(k_classify, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, w, have_mlp ? 1 : 0, bc, rec, n,
                      out);
+  return hipGetLastError();
+}
+
+hipError_t launch_stamp(uint64_t* slot, hipStream_t st) {
+  hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, st, slot);
   return hipGetLastError();
 }
 

@@ -192,6 +192,7 @@ rta_status launch_batch(const rta_pipeline* pipe, const rta_batch* b, rta_hillas
     ea.n_tel = b->n_tel;
     ea.tel = tel_out;
     ea.out = evt_out;
+    ea.done_clock = b->evt_done_clock;
     ea.status = status;
     RTA_HIP(rta::launch_event(ea, st));
   }
@@ -233,6 +234,22 @@ const char* rta_status_str(rta_status s) {
 const char* rta_last_error(void) { return g_err.c_str(); }
 
 int32_t rta_version(void) { return RTA_VERSION; }
+
+rta_status rta_device_clock_hz(int64_t* hz) {
+  if (!hz) return fail(RTA_E_INVALID_ARG, "null hz");
+  int dev = 0, khz = 0;
+  RTA_HIP(hipGetDevice(&dev));
+  RTA_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) return fail(RTA_E_HIP, "device reports no clock rate");
+  *hz = (int64_t)khz * 1000;
+  return RTA_OK;
+}
+
+rta_status rta_device_stamp(uint64_t* slot, rta_stream stream) {
+  if (!slot) return fail(RTA_E_INVALID_ARG, "null slot");
+  RTA_HIP(rta::launch_stamp(slot, (hipStream_t)stream));
+  return RTA_OK;
+}
 
 rta_status rta_device_cus(int32_t* n_cu) {
   if (!n_cu) return fail(RTA_E_INVALID_ARG, "null n_cu");

@@ -130,6 +130,7 @@ struct EventArgs {
   int64_t n_tel;
   rta_hillas_rec* tel;
   rta_event_rec* out;
+  uint64_t* done_clock;   // [n_evt] or null: device clock at each record write
   uint32_t* status;
 };
 
@@ -162,6 +163,7 @@ hipError_t launch_sam_search(const SamDev& d, int end_bin, double* sig, int32_t*
 hipError_t launch_queue_reset(unsigned long long* queue, hipStream_t st);
 hipError_t launch_fused(const FusedArgs& a, const rta_schedule& s, int n_cu, hipStream_t st);
 hipError_t launch_event(const EventArgs& a, hipStream_t st);
+hipError_t launch_stamp(uint64_t* slot, hipStream_t st);
 hipError_t launch_features(const rta_hillas_rec* rec, int64_t n, float* x, hipStream_t st);
 hipError_t launch_classify(const MlpDev& w, bool have_mlp, const rta_boxcut_desc& bc, const rta_hillas_rec* rec,
                            int64_t n, float* out, hipStream_t st);

@@ -52,9 +52,11 @@ class PinnedPool:
         self.max_chunk_elems = max(c[3] for c in self.chunks)
 
 
-def stream(pipe, pinned: PinnedPool, n_chunks, dev, warmup=2):
+def stream(pipe, pinned: PinnedPool, n_chunks, dev, warmup=2, keep_records=False):
     """Reconstruct ``n_chunks`` chunks (cycling through the pinned pool) with
-    copy / compute overlap.  Returns throughput figures."""
+    copy / compute overlap.  Returns throughput figures; with keep_records,
+    also "records": per chunk of the pool, the [n][16] float32 device records
+    of its last pass."""
     import torch
     copy_s, comp_s = torch.cuda.Stream(), torch.cuda.Stream()
     bufs = [torch.empty(pinned.max_chunk_elems, dtype=torch.uint16, device=dev) for _ in range(2)]
@@ -96,10 +98,13 @@ def stream(pipe, pinned: PinnedPool, n_chunks, dev, warmup=2):
     n_ev, nbytes = run(n_chunks, warmup)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"camera_events_per_s": n_ev / dt, "dl0_GBps": nbytes / dt / 1e9,
-            "h2d_payload_GBps": sum(pinned.chunks[(warmup + i) % len(pinned.chunks)][3] * 2
-                                    for i in range(n_chunks)) / dt / 1e9,
-            "chunks": n_chunks, "chunk_bytes_max": pinned.max_chunk_elems * 2, "seconds": dt}
+    res = {"camera_events_per_s": n_ev / dt, "dl0_GBps": nbytes / dt / 1e9,
+           "h2d_payload_GBps": sum(pinned.chunks[(warmup + i) % len(pinned.chunks)][3] * 2
+                                   for i in range(n_chunks)) / dt / 1e9,
+           "chunks": n_chunks, "chunk_bytes_max": pinned.max_chunk_elems * 2, "seconds": dt}
+    if keep_records:
+        res["records"] = outs
+    return res
 
 
 def copy_bandwidth(nbytes, dev, reps=5):
@@ -158,13 +163,37 @@ class PinnedArrayStream:
         self.max_chunk_elems = max(c[5] for c in self.chunks)
 
 
-def paced_latency(pipe, ps: PinnedArrayStream, rate_GBps, n_chunks, dev, warmup=4):
-    """Submit chunks at the paced DL0 rate (each chunk is released when its
-    last byte would have arrived at ``rate_GBps``), copy, reconstruct with
-    stereo and classification, and time each chunk from its arrival to the
-    completion of its event records (HIP events on the device timeline).
-    Every array event of a chunk completes no later than the chunk, so the
-    chunk latency bounds the latency of each of its events."""
+def clock_pair(stream=None):
+    """One reading of the device clock against the host's perf_counter: the
+    stamp is taken between two host readings; returns (host seconds at the
+    midpoint, device ticks, half-width of the window in seconds)."""
+    import torch
+    slot = torch.zeros(1, dtype=torch.int64, device="cuda")
+    best = None
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rta.device_stamp(slot, stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if best is None or t1 - t0 < best[2] * 2:
+            best = (0.5 * (t0 + t1), int(slot.cpu()[0]), 0.5 * (t1 - t0))
+    return best
+
+
+def paced_latency(pipe, ps: PinnedArrayStream, rate_GBps, n_chunks, dev, warmup=4, keep_records=False):
+    """Submit ``n_chunks`` chunks (cycling through the pinned array events) at
+    the paced DL0 rate: a chunk arrives on the host clock when its last byte
+    would have arrived at ``rate_GBps``, and is then copied on a copy stream
+    and reconstructed (calibration to stereo and classification) on a
+    compute stream.  Per array event, two latencies from device clocks:
+    "device": its record write minus the completion of its chunk's
+    host-to-device copy (both stamped on the device clock); "arrival": its
+    record write, mapped to the host clock through clock readings taken
+    before and after the run, minus the chunk's arrival (this includes any
+    wait behind earlier copies).  p50 / p99 over every array event of the
+    timed chunks.  keep_records: also the device records of each chunk's last
+    pass ("records": [(tel, evt)] per chunk of the stream)."""
     import torch
     copy_s, comp_s = torch.cuda.Stream(), torch.cuda.Stream()
     nbuf = 3
@@ -177,34 +206,42 @@ def paced_latency(pipe, ps: PinnedArrayStream, rate_GBps, n_chunks, dev, warmup=
         tel = torch.empty((t_hi - t_lo, 16), dtype=torch.float32, device=dev)
         evt = torch.empty((e_hi - e_lo, 8), dtype=torch.float32, device=dev)
         descs.append((ty, off, eo, tel, evt))
+    n_inst = n_chunks + warmup
+    inst = [i % len(ps.chunks) for i in range(n_inst)]
+    n_ev_inst = np.array([ps.chunks[c][3] - ps.chunks[c][2] for c in inst], np.int64)
+    ev_base = np.zeros(n_inst + 1, np.int64)
+    ev_base[1:] = np.cumsum(n_ev_inst)
+    done_clock = torch.zeros(int(ev_base[-1]), dtype=torch.int64, device=dev)
+    h2d_clock = torch.zeros(n_inst, dtype=torch.int64, device=dev)
     freed = [torch.cuda.Event() for _ in range(nbuf)]
     for ev in freed:
         ev.record(comp_s)
     torch.cuda.synchronize()
-    arrive = [torch.cuda.Event(enable_timing=True) for _ in range(n_chunks + warmup)]
-    done = [torch.cuda.Event(enable_timing=True) for _ in range(n_chunks + warmup)]
-    copied = [torch.cuda.Event() for _ in range(n_chunks + warmup)]
-    sizes = [ps.chunks[i % len(ps.chunks)][5] * 2 for i in range(n_chunks + warmup)]
+    copied = [torch.cuda.Event() for _ in range(n_inst)]
+    sizes = [ps.chunks[c][5] * 2 for c in inst]
+    hz = rta.device_clock_hz()
+    sync0 = clock_pair()
+    arrival = np.zeros(n_inst)
     t_start = time.perf_counter()
     due = t_start
     n_evt = n_tel = nbytes = 0
-    for i in range(n_chunks + warmup):
-        c = i % len(ps.chunks)
+    for i in range(n_inst):
+        c = inst[i]
         t_lo, t_hi, e_lo, e_hi, o0, ne = ps.chunks[c]
         due += sizes[i] / (rate_GBps * 1e9)
         while time.perf_counter() < due:
             pass
+        arrival[i] = due
         b = i % nbuf
-        arrive[i].record(copy_s)
         copy_s.wait_event(freed[b])
         with torch.cuda.stream(copy_s):
             bufs[b][:ne].copy_(ps.host[o0:o0 + ne], non_blocking=True)
+        rta.device_stamp(h2d_clock[i:i + 1], copy_s)
         copied[i].record(copy_s)
         comp_s.wait_event(copied[i])
         ty, off, eo, tel, evt = descs[c]
-        bt = pipe.make_batch(bufs[b], ty, off, eo)
+        bt = pipe.make_batch(bufs[b], ty, off, eo, evt_done_clock=done_clock[ev_base[i]:ev_base[i + 1]])
         pipe.process(bt, tel, evt, stream=comp_s)
-        done[i].record(comp_s)
         freed[b].record(comp_s)
         if i >= warmup:
             n_evt += e_hi - e_lo
@@ -212,10 +249,31 @@ def paced_latency(pipe, ps: PinnedArrayStream, rate_GBps, n_chunks, dev, warmup=
             nbytes += int(ps.dl0[t_lo:t_hi].sum())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    lat = np.array([arrive[i].elapsed_time(done[i]) for i in range(warmup, n_chunks + warmup)])
-    span = arrive[warmup].elapsed_time(done[-1]) * 1e-3
-    return {"array_events_per_s": n_evt / span, "camera_events_per_s": n_tel / span,
-            "dl0_GBps": nbytes / span / 1e9, "paced_GBps": rate_GBps,
-            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
-            "latency_ms_max": float(lat.max()), "chunks": n_chunks,
-            "chunk_bytes_mean": float(np.mean(sizes[warmup:])), "wall_s": wall}
+    sync1 = clock_pair()
+    done = done_clock.cpu().numpy()
+    h2d = h2d_clock.cpu().numpy()
+    inst_of = np.repeat(np.arange(n_inst), n_ev_inst)
+    timed = inst_of >= warmup
+    lat_dev = (done - h2d[inst_of])[timed] / hz
+    # device ticks -> host seconds: the rate measured between the two readings
+    rate = (sync1[1] - sync0[1]) / (sync1[0] - sync0[0])
+    host_done = sync0[0] + (done - sync0[1]) / rate
+    lat_arr = (host_done - arrival[inst_of])[timed]
+    first = ev_base[warmup]
+    span = (done[first:].max() - h2d[warmup]) / hz
+    res = {"array_events": int(timed.sum()), "array_events_per_s": n_evt / span, "camera_events_per_s": n_tel / span,
+           "dl0_GBps": nbytes / span / 1e9, "paced_GBps": rate_GBps,
+           "latency_device_ms_p50": float(np.percentile(lat_dev, 50) * 1e3),
+           "latency_device_ms_p99": float(np.percentile(lat_dev, 99) * 1e3),
+           "latency_device_ms_max": float(lat_dev.max() * 1e3),
+           "latency_device_ms_min": float(lat_dev.min() * 1e3),
+           "latency_arrival_ms_p50": float(np.percentile(lat_arr, 50) * 1e3),
+           "latency_arrival_ms_p99": float(np.percentile(lat_arr, 99) * 1e3),
+           "latency_arrival_ms_max": float(lat_arr.max() * 1e3),
+           "arrival_minus_device_ms_min": float((lat_arr - lat_dev).min() * 1e3),
+           "clock_sync_halfwidth_us": max(sync0[2], sync1[2]) * 1e6,
+           "clock_rate_vs_nominal": rate / hz,
+           "chunks": n_chunks, "chunk_bytes_mean": float(np.mean(sizes[warmup:])), "wall_s": wall}
+    if keep_records:
+        res["records"] = [(d[3], d[4]) for d in descs]
+    return res

@@ -40,12 +40,26 @@ def to_dev(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-def check_records(g_recs, o_recs, pixes, masks, cam_of, tag):
+def oracle_events(ocs, types, blob, offsets, threads=16):
+    """(pix, mask, record) of the oracle for each camera event, the C calls
+    spread over threads (they release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(k):
+        oc = ocs[types[k]]
+        return oc.reconstruct(blob[offsets[k]:offsets[k] + oc.event_elems])
+
+    with ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(one, range(len(types))))
+    return [r[0] for r in res], [r[1] for r in res], [r[2] for r in res]
+
+
+def check_records(g_recs, o_recs, pixes, masks, cam_of, tag, t_input_f32=False):
     bad = []
     for k in range(len(o_recs)):
         ct = cam_of(k)
         mm = par.hillas_mismatches(g_recs[k], o_recs[k], ct.geom.x, ct.geom.y, pixes[k]["q"], pixes[k]["t"],
-                                   masks[k])
+                                   masks[k], t_input_f32=t_input_f32)
         if mm:
             bad.append((k, mm))
     assert not bad, "%s: %d of %d records differ, first: %s" % (tag, len(bad), len(o_recs), bad[:3])
@@ -82,10 +96,10 @@ def calib_parity(ct, traces, dev):
     return cam, oc, out, ref
 
 
-def test_calibrate_c0(torch_dev):
-    ct = dl0sim.camera_c0()
-    say("C0 calibrate: 1855 px x 30 samples, 64 events, seed 0")
-    _, tr = dl0sim.plain_events(ct, 0, 64)
+def test_calibrate_c0(torch_dev, c0_set):
+    """Per-pixel calibration of the whole plain parity set (1000 events)."""
+    ct, cam, oc, tr, pixes, masks, recs = c0_set
+    say("C0 calibrate: 1855 px x 30 samples, %d events, seed 0" % len(tr))
     calib_parity(ct, tr, torch_dev)
 
 
@@ -129,15 +143,16 @@ def test_calibrate_extremes(torch_dev):
 # ---------------------------------------------------------------- cleaning / Hillas
 @pytest.fixture(scope="module")
 def c0_set(torch_dev):
+    """The plain parity set: 1000 events of the 1855-pixel camera, 30
+    samples, single gain, seed 0."""
     ct = dl0sim.camera_c0()
-    say("C0 set: 1855 px x 30 samples, 200 events, seed 0")
-    sh, tr = dl0sim.plain_events(ct, 0, 200)
+    say("C0 set: 1855 px x 30 samples, 1000 events, seed 0")
+    sh, tr = dl0sim.plain_events(ct, 0, 1000)
     cam = rta.Camera.from_type(ct)
     oc = oracle.Camera.from_type(ct)
-    pixes, masks, recs = [], [], []
-    for e in range(len(tr)):
-        p, m, h = oc.reconstruct(tr[e])
-        pixes.append(p); masks.append(m); recs.append(h)
+    E = len(tr)
+    pixes, masks, recs = oracle_events([oc], np.zeros(E, np.int64), tr.reshape(-1),
+                                       np.arange(E, dtype=np.int64) * oc.event_elems)
     return ct, cam, oc, tr, pixes, masks, recs
 
 
@@ -182,7 +197,7 @@ def test_hillas_unfused_c0(torch_dev, c0_set):
     mask = rta.clean(cam, out["D"], out["gain"])
     assert np.array_equal(mask.cpu().numpy(), np.stack(masks))
     h = rta.records(rta.hillas(cam, out["D"], out["gain"], out["t"], mask))
-    check_records(h, recs, pixes, masks, lambda k: ct, "C0 unfused Hillas")
+    check_records(h, recs, pixes, masks, lambda k: ct, "C0 unfused Hillas", t_input_f32=True)
 
 
 def test_fused_equals_unfused_bitwise(torch_dev, c0_set):
@@ -213,7 +228,7 @@ def test_fused_equals_unfused_bitwise(torch_dev, c0_set):
             assert not par.hillas_mismatches(g[k], recs[k], ct.geom.x, ct.geom.y, pixes[k]["q"], pixes[k]["t"],
                                              masks[k])
             assert not par.hillas_mismatches(r[k], recs[k], ct.geom.x, ct.geom.y, pixes[k]["q"], pixes[k]["t"],
-                                             masks[k])
+                                             masks[k], t_input_f32=True)
 
 
 @pytest.fixture(scope="module")
@@ -252,6 +267,49 @@ def run_fused(pool, dev, order=None, schedule=None, do_stereo=False, evt_off=Non
     return pipe, b, tel, evt
 
 
+def test_fused_c0_full_set(torch_dev, c0_set):
+    """The whole plain parity set through the fused kernel in the benchmarked
+    grid schedule and in a persistent schedule."""
+    import torch
+    ct, cam, oc, tr, pixes, masks, recs = c0_set
+    E = len(tr)
+    pipe = rta.Pipeline([cam], do_stereo=False)
+    b = pipe.make_batch(to_dev(tr.reshape(-1), torch_dev), torch.zeros(E, dtype=torch.int32, device=torch_dev),
+                        torch.arange(E, dtype=torch.int64, device=torch_dev) * cam.event_elems)
+    for sched in ((8, 4, 0, 8), (4, 4, 3, 8)):
+        say("C0 fused, %d events, schedule %s" % (E, sched))
+        pipe.set_schedule(*sched)
+        tel, _ = pipe.alloc_outputs(b, torch_dev)
+        pipe.process(b, tel)
+        check_records(rta.records(tel), recs, pixes, masks, lambda k: ct, "C0 fused %s" % (sched,))
+    assert pipe.status() == 0
+
+
+def test_fused_c1_mix_10k(torch_dev):
+    """10^4 unique camera events of the 1:3:6 dual-gain mix (seed 1) through
+    the fused kernel in the benchmarked schedule, every record against the
+    oracle."""
+    import torch
+    pool = W.c1_pool(10_000, seed=1)
+    say("C1 mix: %d unique dual-gain events (%.2f GB), seed 1" % (pool.n, pool.blob.nbytes / 1e9))
+    cams = [rta.Camera.from_type(c) for c in pool.cams]
+    pipe = rta.Pipeline(cams, do_stereo=False)
+    pipe.set_schedule(8, 4, 0, 8)
+    b = pipe.make_batch(to_dev(pool.blob, torch_dev), to_dev(pool.pool_type.astype(np.int32), torch_dev),
+                        to_dev(pool.pool_off.astype(np.int64), torch_dev))
+    tel, _ = pipe.alloc_outputs(b, torch_dev)
+    pipe.process(b, tel)
+    g = rta.records(tel)
+    assert pipe.status() == 0
+    del b
+    ocs = [oracle.Camera.from_type(c) for c in pool.cams]
+    pixes, masks, recs = oracle_events(ocs, pool.pool_type, pool.blob, pool.pool_off)
+    say("  oracle done")
+    check_records(g, recs, pixes, masks, lambda k: pool.cams[pool.pool_type[k]], "C1 mix 10k")
+    # plain images rarely reach the gain switch; the few that do are in the set
+    assert sum(int(r["n_lowgain"]) > 0 for r in recs) > 0
+
+
 def test_fused_c1_mix_parity(torch_dev, c1_set):
     cams, pool, pixes, masks, recs = c1_set
     rng = np.random.default_rng(0)
@@ -267,9 +325,9 @@ def test_fused_c1_mix_parity(torch_dev, c1_set):
 def test_all_schedules_agree(torch_dev, c1_set):
     cams, pool, pixes, masks, recs = c1_set
     base = None
-    for s in rta.list_schedules():
-        if s[2] not in (1, 3):
-            continue
+    scheds = rta.list_schedules()
+    assert len(scheds) == 60 and sum(s[2] == 0 for s in scheds) == 12
+    for s in scheds:
         say("schedule", s)
         _, _, tel, _ = run_fused(pool, torch_dev, schedule=s)
         g = rta.records(tel)
@@ -421,11 +479,12 @@ def test_fused_stereo_recovers_source(torch_dev):
 
 # ---------------------------------------------------------------- full size
 @pytest.mark.parametrize("sched", [(8, 4, 0, 8), (8, 4, 3, 8)])
-def test_full_size_stream_sampled(torch_dev, sched):
+def test_full_size_stream_all_entries(torch_dev, sched):
     """The throughput job (1e6 camera events of the 1:3:6 mix, streamed
     through a device-resident pool; the benchmark's schedule and the
-    persistent form) checked on 150 sampled telescopes against the oracle,
-    event by event."""
+    persistent form): every unique pool entry checked against the oracle at
+    its first position in the stream, and every one of the 1e6 records
+    byte-identical to the record of its pool entry's first position."""
     import torch
     pool = W.c1_pool(600, seed=1)
     n = 1_000_000
@@ -441,25 +500,18 @@ def test_full_size_stream_sampled(torch_dev, sched):
     torch.cuda.synchronize()
     assert pipe.status() == 0
     g = rta.records(tel)
+    # first position of every pool entry in the stream
+    uniq, first = np.unique(idx, return_index=True)
+    assert len(uniq) == pool.n
     ocs = [oracle.Camera.from_type(c) for c in pool.cams]
-    rng = np.random.default_rng(11)
-    sample = np.concatenate([rng.choice(n, 145, replace=False), [0, n - 1, n - 2, n // 2, n // 3]])
-    bad = []
-    for k in sample:
-        t_, o_ = ty[k], off[k]
-        p, m, h = ocs[t_].reconstruct(pool.blob[o_:o_ + pool.cams[t_].event_elems])
-        mm = par.hillas_mismatches(g[k], h, pool.cams[t_].geom.x, pool.cams[t_].geom.y, p["q"], p["t"], m)
-        if mm:
-            bad.append((k, mm))
-    assert not bad, bad[:3]
-    # the same pool entry gives the same record wherever it appears in the stream
-    first = {}
-    for k in range(0, 200_000):
-        e = idx[k]
-        if e in first:
-            assert g[k].tobytes() == g[first[e]].tobytes()
-        else:
-            first[e] = k
+    pixes, masks, recs = oracle_events(ocs, ty[first], pool.blob, off[first])
+    check_records(g[first], recs, pixes, masks, lambda k: pool.cams[ty[first[k]]], "stream first positions")
+    # every record equals the record at its pool entry's first position
+    pos = np.empty(pool.n, np.int64)
+    pos[uniq] = first
+    rows = np.ascontiguousarray(g).view(np.dtype((np.void, g.dtype.itemsize)))
+    same = rows == rows[pos[idx]]
+    assert same.all(), np.flatnonzero(~same)[:5]
 
 
 def test_full_size_array_batch_sampled(torch_dev):
