@@ -288,6 +288,164 @@ __device__ __forceinline__ uint32_t extract_group(const DevCam& c, __amdgpu_buff
 }
 
 // ---------------------------------------------------------------------------
+// Sliding-window argmax that also keeps each pixel's best window (the
+// unfused calibration call reports Nt and the peak of every pixel, not only of
+// the cleaned ones, so re-reading the window samples afterwards would fetch
+// scattered rows of the whole trace a second time).  While the samples
+// stream past, the window ending at slice k replaces the best one when its
+// sum is strictly larger (ties keep the earliest start, as the packed key
+// does), and then the window's four samples, already in registers, are kept
+// packed two per register.  W = 4 only.
+// ---------------------------------------------------------------------------
+template <int PPL>
+struct KeepState {
+  uint32_t ws[PPL];   // running window sum
+  uint32_t key[PPL];  // best (sum << 8) | (255 - start) so far (0 before the first window)
+  uint32_t sv0[PPL];  // samples s*, s*+1 of the best window (low, high half)
+  uint32_t sv1[PPL];  // samples s*+2, s*+3
+};
+
+// (half of word a, the same half of word b) packed low / high: the samples
+// of one pixel at two consecutive slices.
+template <int HALF>
+__device__ __forceinline__ uint32_t pair16(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_perm(b, a, HALF ? 0x07060302u : 0x05040100u);
+}
+
+template <int PPL, int CH, bool TRACK_MAX, bool GUARD, bool FIRST, int J0, int J1>
+__device__ __forceinline__ void keep_slices(const uint32_t (&cur)[CH][PPL / 2], const uint32_t (&prev)[CH][PPL / 2],
+                                            int k0, int T, KeepState<PPL>& st, uint32_t (&rmax)[PPL / 2]) {
+  constexpr int ND = PPL / 2, W = 4;
+#pragma unroll
+  for (int j = J0; j < J1; ++j) {
+    if (GUARD && k0 + j >= T) continue;
+#pragma unroll
+    for (int h = 0; h < ND; ++h) {
+      const uint32_t nw = cur[j][h];
+      if constexpr (TRACK_MAX) rmax[h] = pkmax16(rmax[h], nw);
+      // words of slices k-1, k-2, k-3 (from the previous chunk near its start;
+      // only read once the first window is complete)
+      const uint32_t w1 = j >= 1 ? cur[j - 1][h] : prev[CH - 1][h];
+      const uint32_t w2 = j >= 2 ? cur[j - 2][h] : prev[CH + j - 2][h];
+      const uint32_t w3 = j >= 3 ? cur[j - 3][h] : prev[CH + j - 3][h];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int p = 2 * h + u;
+        const uint32_t x = u ? hi16(nw) : lo16(nw);
+        if (FIRST && j < W) {
+          st.ws[p] += x;
+        } else {
+          const uint32_t od = j >= W ? cur[j - W][h] : prev[CH + j - W][h];
+          st.ws[p] += x - (u ? hi16(od) : lo16(od));
+        }
+        if (!FIRST || j >= W - 1) {
+          // the window starting at k - 3 wins on a larger sum; on an equal
+          // sum the earlier start, already held, has the larger key
+          const uint32_t nk = (st.ws[p] << 8) | (uint32_t)(255 - (k0 + j - (W - 1)));
+          const bool better = nk > st.key[p];
+          st.key[p] = better ? nk : st.key[p];
+          st.sv0[p] = better ? (u ? pair16<1>(w3, w2) : pair16<0>(w3, w2)) : st.sv0[p];
+          st.sv1[p] = better ? (u ? pair16<1>(w1, nw) : pair16<0>(w1, nw)) : st.sv1[p];
+        }
+      }
+    }
+  }
+}
+
+template <int PPL, int CH, bool TRACK_MAX>
+__device__ __forceinline__ void window_keep(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t sbase, uint32_t stride,
+                                            int T, KeepState<PPL>& st, uint32_t (&rmax)[PPL / 2]) {
+  constexpr int W = 4;
+  static_assert(CH % W == 0 && CH >= W && CH <= 16, "chunk must be a multiple of the window, at most 16");
+  constexpr int ND = PPL / 2;
+  uint32_t A[CH][ND], B[CH][ND];
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    st.ws[p] = 0; st.key[p] = 0; st.sv0[p] = 0; st.sv1[p] = 0;
+  }
+  const int nchunk = (T + CH - 1) / CH;
+  const int nfull = T / CH;
+  load_chunk<PPL, CH>(A, r, voff, sbase, stride, 0);
+  if (nchunk > 1) load_chunk<PPL, CH>(B, r, voff, sbase, stride, CH);
+  if (nfull >= 1)
+    keep_slices<PPL, CH, TRACK_MAX, false, true, 0, CH>(A, A, 0, T, st, rmax);
+  else
+    keep_slices<PPL, CH, TRACK_MAX, true, true, 0, CH>(A, A, 0, T, st, rmax);
+  for (int c = 1; c < nchunk; c += 2) {
+    const int k0 = c * CH;
+    if (c < nfull) {
+      keep_slices<PPL, CH, TRACK_MAX, false, false, 0, W>(B, A, k0, T, st, rmax);
+      if (c + 1 < nchunk) load_chunk<PPL, CH>(A, r, voff, sbase, stride, k0 + CH);
+      keep_slices<PPL, CH, TRACK_MAX, false, false, W, CH>(B, A, k0, T, st, rmax);
+    } else {
+      keep_slices<PPL, CH, TRACK_MAX, true, false, 0, CH>(B, A, k0, T, st, rmax);
+    }
+    if (c + 1 >= nchunk) break;
+    const int k1 = k0 + CH;
+    if (c + 1 < nfull) {
+      keep_slices<PPL, CH, TRACK_MAX, false, false, 0, W>(A, B, k1, T, st, rmax);
+      if (c + 2 < nchunk) load_chunk<PPL, CH>(B, r, voff, sbase, stride, k1 + CH);
+      keep_slices<PPL, CH, TRACK_MAX, false, false, W, CH>(A, B, k1, T, st, rmax);
+    } else {
+      keep_slices<PPL, CH, TRACK_MAX, true, false, 0, CH>(A, B, k1, T, st, rmax);
+    }
+  }
+}
+
+// Extraction of one pixel group with its best windows kept: the high gain,
+// then, when any lane of the wave owns a switched pixel, the low gain, whose
+// window replaces the high-gain one for the switched pixels.  Returns the
+// switch mask; st holds the selected gain's windows.
+template <int PPL, int CH>
+__device__ __forceinline__ uint32_t keep_group(const DevCam& c, __amdgpu_buffer_rsrc_t r, int pix0, int np, int T,
+                                               bool dual, KeepState<PPL>& st) {
+  uint32_t rmax[PPL / 2];
+#pragma unroll
+  for (int h = 0; h < PPL / 2; ++h) rmax[h] = 0;
+  const uint32_t voff = (uint32_t)pix0 * 2u, stride = (uint32_t)np * 2u;
+  uint32_t sw = 0;
+  if (dual) {
+    window_keep<PPL, CH, true>(r, voff, 0u, stride, T, st, rmax);
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const uint32_t m = (p & 1) ? hi16(rmax[p >> 1]) : lo16(rmax[p >> 1]);
+      if ((int)m >= c.hg_switch) sw |= 1u << p;
+    }
+    if (__ballot(sw != 0u)) {
+      KeepState<PPL> lg;
+      uint32_t unused[PPL / 2];
+      window_keep<PPL, CH, false>(r, voff, (uint32_t)T * stride, stride, T, lg, unused);
+#pragma unroll
+      for (int p = 0; p < PPL; ++p)
+        if ((sw >> p) & 1u) {
+          st.key[p] = lg.key[p];
+          st.sv0[p] = lg.sv0[p];
+          st.sv1[p] = lg.sv1[p];
+        }
+    }
+  } else {
+    window_keep<PPL, CH, false>(r, voff, 0u, stride, T, st, rmax);
+  }
+  return sw;
+}
+
+// Nt = sum_k k*(256*x[s*+k] - P) and the earliest in-window peak from a kept
+// window (samples x0..x3 = low / high halves of sv0, sv1).
+__device__ __forceinline__ int32_t kept_nt(uint32_t sv0, uint32_t sv1, int32_t P, int s, int* peak) {
+  const uint32_t x[4] = {lo16(sv0), hi16(sv0), lo16(sv1), hi16(sv1)};
+  int32_t nt = 0;
+  uint32_t pmax = x[0];
+  int pk = s;
+#pragma unroll
+  for (int k = 1; k < 4; ++k) {
+    nt += k * (256 * (int32_t)x[k] - P);
+    if (x[k] > pmax) { pmax = x[k]; pk = s + k; }
+  }
+  *peak = pk;
+  return nt;
+}
+
+// ---------------------------------------------------------------------------
 // Window placement by the other extractors.  They produce the same packed key
 // (S << 8) | (255 - s*) as the sliding window, so every later step is shared.
 // ---------------------------------------------------------------------------
@@ -1076,6 +1234,34 @@ __global__ __launch_bounds__(NT) void k_calibrate(DevCam c, const uint16_t* __re
   const uint16_t* ev = traces + e * c.event_elems;
   const size_t ob = (size_t)e * N;
   const __amdgpu_buffer_rsrc_t r = event_rsrc(ev, c.event_elems);
+  if constexpr (EX == kExSliding && W == 4) {
+    // the trace is read once: every pixel's window kept while it streams
+    const int npass = (N + NT * PPL - 1) / (NT * PPL);
+    for (int ps = 0; ps < npass; ++ps) {
+      const int pix0 = (ps * NT + (int)threadIdx.x) * PPL;
+      KeepState<PPL> st;
+      const uint32_t sw = keep_group<PPL, 2 * W>(c, r, pix0, np, T, c.n_gain == 2, st);
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        const int i = pix0 + p;
+        if (i >= N) break;
+        const int g = (sw >> p) & 1;
+        const int s = 255 - (int)(st.key[p] & 255u);
+        const int32_t P = c.P256[g * np + i];
+        const int32_t d = key_to_d<W>(st.key[p], P);
+        int pk;
+        const int32_t nt = kept_nt(st.sv0[p], st.sv1[p], P, s, &pk);
+        if (S) S[ob + i] = (int32_t)(st.key[p] >> 8);
+        if (D) D[ob + i] = d;
+        if (sstar) sstar[ob + i] = (uint8_t)s;
+        if (peak) peak[ob + i] = (uint8_t)pk;
+        if (gain) gain[ob + i] = (uint8_t)g;
+        if (q) q[ob + i] = (float)d / (256.0f * c.a[g * np + i]);
+        if (t) t[ob + i] = (float)peak_time<W>(s, nt, d);
+      }
+    }
+    return;
+  }
   extract_event<EX, PPL, W, 2 * W, NT>(c, r, ev, rows, &start, xrow, [&](int pix0, const uint32_t (&key)[PPL],
                                                                          uint32_t sw) {
 #pragma unroll
@@ -1346,13 +1532,14 @@ __global__ __launch_bounds__(256) void k_classify(MlpDev w, int have_mlp, rta_bo
 // ---------------------------------------------------------------------------
 constexpr int kUnfusedNT = 256;
 constexpr int kUnfusedPPL = 4;
+constexpr int kKeepPPL = 2;  // sliding-window calibrate: the kept windows take registers
 
 template <int W>
 hipError_t launch_calibrate_w(const DevCam& c, int ex, const uint16_t* tr, int64_t n, int32_t* S, int32_t* D,
                               uint8_t* ss, uint8_t* pk, uint8_t* g, float* q, float* t, hipStream_t st) {
   switch (ex) {
     case kExSliding:
-      hipLaunchKernelGGL((k_calibrate<kExSliding, kUnfusedPPL, W, kUnfusedNT>), dim3((unsigned)n), dim3(kUnfusedNT),
+      hipLaunchKernelGGL((k_calibrate<kExSliding, kKeepPPL, W, kUnfusedNT>), dim3((unsigned)n), dim3(kUnfusedNT),
                          0, st, c, tr, S, D, ss, pk, g, q, t);
       break;
     case kExFixed:
