@@ -889,9 +889,8 @@ __device__ __forceinline__ uint32_t pixel_flag(const DevCam& c, int g, int i, in
 // Workgroup-shared state of one camera event.
 // ---------------------------------------------------------------------------
 struct TelSmem {
-  int32_t D[kMaxPix];        // calibrated charge (Q8); reused as union-find parents
-  uint16_t meta[kMaxPix];    // s* | gain << 8
-  uint8_t flag[kMaxPix];     // bit 0: D >= Tb, bit 1: D >= Tp
+  uint32_t key[kMaxPix];     // (S << 8) | (255 - s*) per pixel; reused as union-find parents
+  uint8_t flag[kMaxPix];     // bit 0: D >= Tb, bit 1: D >= Tp, bit 2: low gain
   uint64_t mbits[kMaxWords]; // cleaning mask, one word per 64 pixels
   int32_t wbase[kMaxWords + 1];
   uint16_t list[kMaxPix];    // slot -> pixel
@@ -961,9 +960,8 @@ __device__ __forceinline__ int extract_phase(const DevCam& c, const uint16_t* __
         int32_t Pv = P[p], tb = Tb[p], tp = Tp[p];
         if (g) { Pv = c.P256[np + i]; tb = c.thr_bnd[np + i]; tp = c.thr_pic[np + i]; }
         const int32_t d = key_to_d<W>(key[p], Pv);
-        sm.D[i] = d;
-        sm.meta[i] = (uint16_t)((255u - (key[p] & 255u)) | ((uint32_t)g << 8));
-        sm.flag[i] = (uint8_t)((uint32_t)(d >= tb) | ((uint32_t)(d >= tp) << 1));
+        sm.key[i] = key[p];
+        sm.flag[i] = (uint8_t)((uint32_t)(d >= tb) | ((uint32_t)(d >= tp) << 1) | ((uint32_t)g << 2));
         nlow += g;
       }
     }
@@ -980,7 +978,7 @@ __device__ __forceinline__ void mask_phase(const DevCam& c, TelSmem& sm) {
     const int i = base + lane;
     bool m = false;
     if (i < N) {
-      const uint32_t f = sm.flag[i];
+      const uint32_t f = sm.flag[i] & 3u;
       if (f) {
         const int4 nv = *reinterpret_cast<const int4*>(c.nbr + (size_t)i * kNbrCols);
         const int16_t* nb = reinterpret_cast<const int16_t*>(&nv);
@@ -1033,11 +1031,12 @@ __device__ __forceinline__ void list_phase(const DevCam& c, TelSmem& sm, const u
       int g;
       double t;
       if constexpr (FUSED) {
-        d = sm.D[i];
-        const uint32_t meta = sm.meta[i];
-        g = (int)(meta >> 8);
-        const int s = (int)(meta & 255u);
-        const int32_t nt = window_nt<W>(ev + (size_t)g * c.n_samp * np + i, np, s, c.P256[g * np + i], nullptr);
+        const uint32_t k = sm.key[i];
+        g = (int)(sm.flag[i] >> 2);
+        const int s = 255 - (int)(k & 255u);
+        const int32_t P = c.P256[g * np + i];
+        d = key_to_d<W>(k, P);
+        const int32_t nt = window_nt<W>(ev + (size_t)g * c.n_samp * np + i, np, s, P, nullptr);
         t = peak_time<W>(s, nt, d);
       } else {
         d = Dg[i];
@@ -1074,10 +1073,11 @@ __device__ __forceinline__ void uf_union(int32_t* par, int a, int b) {
 }
 
 // Phase 5: islands = roots of the union-find forest over mask slots.
-// Returns this thread's root count.  sm.D is reused for the parents.
+// Returns this thread's root count.  The per-pixel keys (no longer needed)
+// hold the parents.
 template <int NT>
 __device__ __forceinline__ int islands_phase(const DevCam& c, TelSmem& sm, int n) {
-  int32_t* par = sm.D;
+  int32_t* par = reinterpret_cast<int32_t*>(sm.key);
   for (int j = threadIdx.x; j < n; j += NT) par[j] = j;
   __syncthreads();
   for (int j = threadIdx.x; j < n; j += NT) {
