@@ -889,22 +889,51 @@ __device__ __forceinline__ uint32_t pixel_flag(const DevCam& c, int g, int i, in
 // Workgroup-shared state of one camera event.
 // ---------------------------------------------------------------------------
 struct TelSmem {
-  uint32_t key[kMaxPix];     // (S << 8) | (255 - s*) per pixel; reused as union-find parents
+  union {
+    uint32_t key[kMaxPix];   // (S << 8) | (255 - s*) per pixel; reused as union-find parents
+    uint32_t rows[kMaxPix];  // global peak: per-wave slice sums; neighbour peak: key hand-over (extraction only)
+  };
   uint8_t flag[kMaxPix];     // bit 0: D >= Tb, bit 1: D >= Tp, bit 2: low gain
   uint64_t mbits[kMaxWords]; // cleaning mask, one word per 64 pixels
   int32_t wbase[kMaxWords + 1];
-  uint16_t list[kMaxPix];    // slot -> pixel
-  union {
-    float q[kMaxPix];        // charge per slot, p.e.
-    uint32_t rows[kMaxPix];  // global peak: per-wave slice sums (extraction only)
-  };
+  uint16_t list[kMaxPix];    // slot -> pixel | gain << 15
   union alignas(16) {        // 16-byte aligned: slices are staged with 16-byte stores
-    double t[kMaxPix];       // peak time per slot, samples
+    struct {
+      // per slot, fused path: D and Nt in their low 28 bits (both fit in 28
+      // signed bits), s* split over the top 4 bits of each; unfused path:
+      // D in dq, the float bits of the given peak time in nt
+      uint32_t dq[kMaxPix];
+      uint32_t nt[kMaxPix];
+    } slot;
     uint16_t xrow[kNbrRows * (kMaxPix + 8)];  // neighbour peak: staged slices + zero slot (extraction only)
   };
   double red[16 * 8];        // cross-wave reduction scratch
   int32_t start;             // global peak window start
 };
+
+__device__ __forceinline__ int32_t sext28(uint32_t v) { return (int32_t)(v << 4) >> 4; }
+
+// Charge of slot j: q = D / (256 a), formed where it is used (the same float
+// every time).
+template <bool FUSED>
+__device__ __forceinline__ float slot_q(const DevCam& c, const TelSmem& sm, int j, int i) {
+  const int g = sm.list[j] >> 15;
+  const int32_t D = FUSED ? sext28(sm.slot.dq[j]) : (int32_t)sm.slot.dq[j];
+  return (float)D / (256.0f * c.a[g * c.n_pix_pad + i]);
+}
+
+// Peak time of slot j (samples): s* + Nt / D from the packed slot, or the
+// given float time on the unfused path.
+template <bool FUSED, int W>
+__device__ __forceinline__ double slot_t(const TelSmem& sm, int j) {
+  const uint32_t a = sm.slot.dq[j], b = sm.slot.nt[j];
+  if constexpr (FUSED) {
+    const int s = (int)(((a >> 28) << 4) | (b >> 28));
+    return peak_time<W>(s, sext28(b), sext28(a));
+  } else {
+    return (double)__uint_as_float(b);
+  }
+}
 
 template <typename T, int NV, int NT>
 __device__ __forceinline__ void block_sum(T (&v)[NV], double* red_raw) {
@@ -1027,25 +1056,22 @@ __device__ __forceinline__ void list_phase(const DevCam& c, TelSmem& sm, const u
     const uint64_t bits = sm.mbits[base >> 6];
     if ((bits >> lane) & 1ull) {
       const int j = sm.wbase[base >> 6] + __popcll(bits & ((1ull << lane) - 1ull));
-      int32_t d;
-      int g;
-      double t;
       if constexpr (FUSED) {
         const uint32_t k = sm.key[i];
-        g = (int)(sm.flag[i] >> 2);
+        const int g = (int)(sm.flag[i] >> 2);
         const int s = 255 - (int)(k & 255u);
         const int32_t P = c.P256[g * np + i];
-        d = key_to_d<W>(k, P);
+        const int32_t d = key_to_d<W>(k, P);
         const int32_t nt = window_nt<W>(ev + (size_t)g * c.n_samp * np + i, np, s, P, nullptr);
-        t = peak_time<W>(s, nt, d);
+        sm.list[j] = (uint16_t)(i | (g << 15));
+        sm.slot.dq[j] = ((uint32_t)d & 0x0FFFFFFFu) | ((uint32_t)(s >> 4) << 28);
+        sm.slot.nt[j] = ((uint32_t)nt & 0x0FFFFFFFu) | ((uint32_t)(s & 15) << 28);
       } else {
-        d = Dg[i];
-        g = gg ? (int)gg[i] : 0;
-        t = (double)tg[i];
+        const int g = gg ? (int)gg[i] : 0;
+        sm.list[j] = (uint16_t)(i | (g << 15));
+        sm.slot.dq[j] = (uint32_t)Dg[i];
+        sm.slot.nt[j] = __float_as_uint(tg[i]);
       }
-      sm.list[j] = (uint16_t)i;
-      sm.q[j] = (float)d / (256.0f * c.a[g * np + i]);
-      sm.t[j] = t;
     }
   }
 }
@@ -1081,7 +1107,7 @@ __device__ __forceinline__ int islands_phase(const DevCam& c, TelSmem& sm, int n
   for (int j = threadIdx.x; j < n; j += NT) par[j] = j;
   __syncthreads();
   for (int j = threadIdx.x; j < n; j += NT) {
-    const int i = sm.list[j];
+    const int i = sm.list[j] & 0x7FFF;
     const int4 nv = *reinterpret_cast<const int4*>(c.nbr + (size_t)i * kNbrCols);
     const int16_t* nb = reinterpret_cast<const int16_t*>(&nv);
 #pragma unroll
@@ -1103,13 +1129,13 @@ __device__ __forceinline__ int islands_phase(const DevCam& c, TelSmem& sm, int n
 // digits when the width is small).  The time regression (sums of l and t,
 // their centred cross products) is accumulated in FP64: times are absolute
 // sample numbers, so FP32 would cancel most digits of small time gradients.
-template <int NT>
+template <int NT, int W, bool FUSED>
 __device__ __forceinline__ void hillas_phase(const DevCam& c, TelSmem& sm, int n, int roots, int nlow,
                                              rta_hillas_rec* out) {
   float v1[6] = {0.f, 0.f, 0.f, 0.f, (float)roots, (float)nlow};
   for (int j = threadIdx.x; j < n; j += NT) {
-    const int i = sm.list[j];
-    const float q = sm.q[j];
+    const int i = sm.list[j] & 0x7FFF;
+    const float q = slot_q<FUSED>(c, sm, j, i);
     v1[0] += q;
     v1[1] += q * c.x[i];
     v1[2] += q * c.y[i];
@@ -1133,8 +1159,8 @@ __device__ __forceinline__ void hillas_phase(const DevCam& c, TelSmem& sm, int n
   const float xm = v1[1] / S, ym = v1[2] / S;
   float v2[3] = {0.f, 0.f, 0.f};
   for (int j = threadIdx.x; j < n; j += NT) {
-    const int i = sm.list[j];
-    const float q = sm.q[j], dx = c.x[i] - xm, dy = c.y[i] - ym;
+    const int i = sm.list[j] & 0x7FFF;
+    const float q = slot_q<FUSED>(c, sm, j, i), dx = c.x[i] - xm, dy = c.y[i] - ym;
     v2[0] += q * dx * dx;
     v2[1] += q * dy * dy;
     v2[2] += q * dx * dy;
@@ -1149,8 +1175,8 @@ __device__ __forceinline__ void hillas_phase(const DevCam& c, TelSmem& sm, int n
   const float cs = cosf(psi), sn = sinf(psi);
   double v3[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // q l^3, q l^4, q w^2, l, t
   for (int j = threadIdx.x; j < n; j += NT) {
-    const int i = sm.list[j];
-    const float q = sm.q[j], dx = c.x[i] - xm, dy = c.y[i] - ym;
+    const int i = sm.list[j] & 0x7FFF;
+    const float q = slot_q<FUSED>(c, sm, j, i), dx = c.x[i] - xm, dy = c.y[i] - ym;
     const float l = dx * cs + dy * sn;
     const float w = dy * cs - dx * sn;
     const float l2 = l * l;
@@ -1158,17 +1184,17 @@ __device__ __forceinline__ void hillas_phase(const DevCam& c, TelSmem& sm, int n
     v3[1] += (double)(q * l2 * l2);
     v3[2] += (double)(q * w * w);
     v3[3] += (double)l;
-    v3[4] += sm.t[j];
+    v3[4] += slot_t<FUSED, W>(sm, j);
   }
   block_sum<double, 5, NT>(v3, sm.red);
   const double lbar = v3[3] / (double)n, tbar = v3[4] / (double)n;
   double v4[2] = {0.0, 0.0};
   for (int j = threadIdx.x; j < n; j += NT) {
-    const int i = sm.list[j];
+    const int i = sm.list[j] & 0x7FFF;
     const float dx = c.x[i] - xm, dy = c.y[i] - ym;
     const double l = (double)(dx * cs + dy * sn) - lbar;
     v4[0] += l * l;
-    v4[1] += l * (sm.t[j] - tbar);
+    v4[1] += l * (slot_t<FUSED, W>(sm, j) - tbar);
   }
   block_sum<double, 2, NT>(v4, sm.red);
   r.cog_x = xm;
@@ -1205,7 +1231,7 @@ __device__ __forceinline__ void process_telescope(const DevCam& c, const uint16_
   list_phase<NT, W, true>(c, sm, ev, nullptr, nullptr, nullptr);
   __syncthreads();
   const int roots = islands_phase<NT>(c, sm, n);
-  hillas_phase<NT>(c, sm, n, roots, nlow, out);
+  hillas_phase<NT, W, true>(c, sm, n, roots, nlow, out);
 }
 
 __device__ __forceinline__ void bad_record(rta_hillas_rec* out) {
@@ -1327,7 +1353,7 @@ __global__ __launch_bounds__(NT) void k_hillas(DevCam c, const int32_t* __restri
   list_phase<NT, W, false>(c, sm, nullptr, D + ob, gain ? gain + ob : nullptr, t + ob);
   __syncthreads();
   const int roots = islands_phase<NT>(c, sm, n);
-  hillas_phase<NT>(c, sm, n, roots, nlow, out + e);
+  hillas_phase<NT, W, false>(c, sm, n, roots, nlow, out + e);
 }
 
 __global__ void k_queue_reset(unsigned long long* q) {
