@@ -649,13 +649,13 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
   // position p = 8 g + m lives in word 8 g + (m ^ (g & 7)): consecutive
   // lanes reading consecutive positions touch distinct banks
   auto slot = [](uint32_t j) { return (j & ~7u) | ((j ^ (j >> 3)) & 7u); };
-  uint32_t nb[MAXK][3];  // six neighbour words per position, packed 16-bit slots (Npad if missing)
+  uint32_t nb[MAXK][3];  // six neighbour words per position: LDS byte offsets, 16 bits each (word Npad if missing)
   uint32_t ring[MAXK][W - 1];
   uint32_t best[MAXK], hmax[MAXK], hmax2[MAXK], pix[MAXK];
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) {
     const int p = (int)threadIdx.x + k * NT;
-    nb[k][0] = nb[k][1] = nb[k][2] = (uint32_t)np * 0x10001u;
+    nb[k][0] = nb[k][1] = nb[k][2] = (uint32_t)np * 8u * 0x10001u;
     pix[k] = 0;
     if (p < N) {
       const int4 v = *reinterpret_cast<const int4*>(c.lat + (size_t)p * kNbrCols);
@@ -664,7 +664,7 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
       for (int h = 0; h < 3; ++h) {
         const uint32_t lo = (w3[h] & 0x8000u) ? (uint32_t)np : slot(w3[h] & 0xffffu);
         const uint32_t hi = (w3[h] & 0x80000000u) ? (uint32_t)np : slot(w3[h] >> 16);
-        nb[k][h] = lo | (hi << 16);
+        nb[k][h] = (lo << 3) | (hi << 19);  // (Npad + 1) * 8 bytes < 2^16
       }
       pix[k] = (uint32_t)v.w & 0xffffu;
     }
@@ -715,16 +715,34 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
     for (int k = 0; k < MAXK; ++k) {
       const int p = (int)threadIdx.x + k * NT;
       if (p >= N) continue;
-      uint32_t y[kNbrRows] = {0u, 0u, 0u, 0u};
+      uint64_t v[6];
 #pragma unroll
       for (int m = 0; m < 6; ++m) {
-        const int jn = (int)((nb[k][m >> 1] >> ((m & 1) * 16)) & 0xffffu);
-        const uint64_t v = xs[jn];
-        const uint32_t v01 = (uint32_t)v, v23 = (uint32_t)(v >> 32);
-        y[0] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v01), row_lo, y[0], false);
-        y[1] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v01), row_hi, y[1], false);
-        y[2] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v23), row_lo, y[2], false);
-        y[3] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v23), row_hi, y[3], false);
+        const uint32_t off = (nb[k][m >> 1] >> ((m & 1) * 16)) & 0xffffu;
+        v[m] = *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(xs) + off);
+      }
+      // the six neighbours' slices summed two at a time in saturating 16-bit
+      // halves; a sum that reached 65535 (so maybe more) is formed again in
+      // 32 bits, for the whole wave when any lane needs it
+      us2 s01 = __builtin_bit_cast(us2, (uint32_t)v[0]), s23 = __builtin_bit_cast(us2, (uint32_t)(v[0] >> 32));
+#pragma unroll
+      for (int m = 1; m < 6; ++m) {
+        s01 = __builtin_elementwise_add_sat(s01, __builtin_bit_cast(us2, (uint32_t)v[m]));
+        s23 = __builtin_elementwise_add_sat(s23, __builtin_bit_cast(us2, (uint32_t)(v[m] >> 32)));
+      }
+      const us2 smax = __builtin_elementwise_max(s01, s23);
+      uint32_t y[kNbrRows] = {s01[0], s01[1], s23[0], s23[1]};
+      if (__ballot(smax[0] == 0xffffu || smax[1] == 0xffffu)) {
+#pragma unroll
+        for (int u = 0; u < kNbrRows; ++u) y[u] = 0;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          const uint32_t v01 = (uint32_t)v[m], v23 = (uint32_t)(v[m] >> 32);
+          y[0] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v01), row_lo, y[0], false);
+          y[1] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v01), row_hi, y[1], false);
+          y[2] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v23), row_lo, y[2], false);
+          y[3] = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v23), row_hi, y[3], false);
+        }
       }
       const uint64_t own = xs[slot((uint32_t)p)];
       const uint32_t o01 = (uint32_t)own, o23 = (uint32_t)(own >> 32);
