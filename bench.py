@@ -186,12 +186,13 @@ def latency_run(args, dev, network):
     while got < args.latency_events:
         got += int(per[(warmup + n_chunks) % len(per)])
         n_chunks += 1
-    r = st.paced_latency(pipe, ps, args.rate, n_chunks, dev, warmup=warmup)
+    r = st.paced_latency(pipe, ps, args.rate, n_chunks, dev, warmup=warmup, classify_after_hillas=True)
     if pipe.status():
         raise RuntimeError("device status word %#x in the latency run" % pipe.status())
     r["pool_array_events"] = args.latency_pool
     r["pool_telescopes"] = int(len(aw.tel_type))
-    r["mix"] = "1855x40 : 1764x25 : 2048x128 = 1:1:8, multiplicity 2..40, network + box-cut fallback attached"
+    r["mix"] = ("1855x40 : 1764x25 : 2048x128 = 1:1:8, multiplicity 2..40, network + box-cut fallback "
+                "classifying each telescope in the reconstruction kernel after Hillas")
     log("latency run: %s (%.1f s)" % (r, time.time() - t0))
     return r
 
@@ -235,23 +236,32 @@ def array_batch_run(args, dev, stream, network):
     if status:
         raise RuntimeError("device status word %#x" % status)
     ms = a.elapsed_time(z) / args.array_steps
-    # the same job with the network attached: classification in the per-event pass
-    net_ms = None
+    # the same job with the network attached: each telescope classified in the
+    # reconstruction kernel right after Hillas (per-telescope scores to
+    # tel_class), and, for comparison, in the per-event pass
+    net_ms = evt_pass_ms = None
     if network is not None:
         pipe.attach_mlp(*network)
-        with torch.cuda.stream(stream):
-            g2 = pipe.capture(b, tel, evt)
-            g2.launch(stream)
-            stream.synchronize()
-            a.record(stream)
-            for _ in range(args.array_steps):
+        cls = torch.empty((len(ty), 2), dtype=torch.float32, device=dev)
+        bf = pipe.make_batch(blob_d, ty_d, off_d, eo_d, tel_class=cls)
+
+        def timed_graph(batch):
+            with torch.cuda.stream(stream):
+                g2 = pipe.capture(batch, tel, evt)
                 g2.launch(stream)
-            z.record(stream)
-            stream.synchronize()
-        net_ms = a.elapsed_time(z) / args.array_steps
-        if pipe.status():
-            raise RuntimeError("device status word %#x with the network" % pipe.status())
-        del g2
+                stream.synchronize()
+                a.record(stream)
+                for _ in range(args.array_steps):
+                    g2.launch(stream)
+                z.record(stream)
+                stream.synchronize()
+            if pipe.status():
+                raise RuntimeError("device status word %#x with the network" % pipe.status())
+            return a.elapsed_time(z) / args.array_steps
+
+        net_ms = timed_graph(bf)
+        evt_pass_ms = timed_graph(b)
+        del bf, cls
     dl0 = np.array([c.dl0_bytes for c in aw.pool.cams], np.int64)
     ev = rta.records(evt, rta.EVENT_DTYPE)
     n_evt, n_tel = args.array_events, len(ty)
@@ -262,9 +272,13 @@ def array_batch_run(args, dev, stream, network):
          "pool_array_events": args.array_pool, "pool_GB": aw.pool.blob.nbytes / 1e9,
          "schedule": list(best), "steps": args.array_steps, "graph": True}
     if net_ms is not None:
-        r["with_network"] = {"gpu_ms_per_step": net_ms, "array_events_per_s": n_evt / (net_ms * 1e-3),
-                             "classification_ms_per_step": net_ms - ms,
-                             "classification_ns_per_array_event": (net_ms - ms) * 1e6 / n_evt}
+        r["with_network"] = {
+            "classified_after_hillas": {"gpu_ms_per_step": net_ms, "array_events_per_s": n_evt / (net_ms * 1e-3),
+                                        "classification_ms_per_step": net_ms - ms,
+                                        "classification_ns_per_telescope": (net_ms - ms) * 1e6 / n_tel},
+            "classified_in_event_pass": {"gpu_ms_per_step": evt_pass_ms,
+                                         "classification_ms_per_step": evt_pass_ms - ms,
+                                         "classification_ns_per_telescope": (evt_pass_ms - ms) * 1e6 / n_tel}}
     log("array batch: %s (%.1f s)" % (r, time.time() - t0))
     del graph, blob_d, b, tel, evt, tb
     torch.cuda.empty_cache()

@@ -178,6 +178,12 @@ typedef struct rta_batch {
   int64_t n_tel;
   uint64_t* evt_done_clock;     /* NULLABLE [n_evt]: with do_stereo, the device clock (see
                                    rta_device_clock_hz) at which each event record was written */
+  float* tel_class;             /* NULLABLE [n_tel][2]: with a classifier attached
+                                   (rta_pipeline_attach_mlp), each telescope is classified in the
+                                   reconstruction kernel right after its Hillas parameters: gamma
+                                   score and log10(E / TeV) here (NaN without a valid image),
+                                   RTA_FLAG_MLP_FALLBACK in its record; the per-event pass then
+                                   aggregates these.  Values equal rta_classify's. */
 } rta_batch;
 
 typedef struct rta_pipeline_params {
@@ -464,11 +470,13 @@ rta_status rta_features(const rta_hillas_rec* rec, int64_t n, float* x, rta_stre
 rta_status rta_classify(rta_mlp* m, const rta_boxcut_desc* bc, const rta_hillas_rec* rec, int64_t n, float* out,
                         rta_stream stream);
 
-/* Attach (m != NULL) or detach the network and box cuts to a pipeline with
- * do_stereo: the per-event pass then classifies every telescope, sets
- * RTA_FLAG_MLP_FALLBACK in records that used the box cuts, and writes the
- * size-weighted mean score and log10 E to the event record.  The network must
- * outlive the pipeline or be detached first.  bc: HOST memory. */
+/* Attach (m != NULL) or detach the network and box cuts to a pipeline.  Every
+ * telescope is then classified: in the reconstruction kernel right after its
+ * Hillas parameters when the batch gives rta_batch.tel_class, otherwise (with
+ * do_stereo) in the per-event pass; RTA_FLAG_MLP_FALLBACK marks records that
+ * used the box cuts.  With do_stereo the event record gets the size-weighted
+ * mean score and log10 E.  The network must outlive the pipeline or be
+ * detached first.  bc: HOST memory. */
 rta_status rta_pipeline_attach_mlp(rta_pipeline* pipe, rta_mlp* m, const rta_boxcut_desc* bc);
 
 /* ------------------------------------------------------------------------

@@ -65,7 +65,7 @@ class CameraInfo(ctypes.Structure):
 class Batch(ctypes.Structure):
     _fields_ = [("traces", ctypes.c_void_p), ("traces_len", ctypes.c_int64), ("evt_tel_off", ctypes.c_void_p),
                 ("tel_type", ctypes.c_void_p), ("tel_trace_off", ctypes.c_void_p), ("n_evt", ctypes.c_int64),
-                ("n_tel", ctypes.c_int64), ("evt_done_clock", ctypes.c_void_p)]
+                ("n_tel", ctypes.c_int64), ("evt_done_clock", ctypes.c_void_p), ("tel_class", ctypes.c_void_p)]
 
 
 class PipelineParams(ctypes.Structure):
@@ -391,9 +391,11 @@ class Pipeline:
         return s.as_tuple()
 
     @staticmethod
-    def make_batch(traces, tel_type, tel_trace_off, evt_tel_off=None, evt_done_clock=None):
+    def make_batch(traces, tel_type, tel_trace_off, evt_tel_off=None, evt_done_clock=None, tel_class=None):
         """evt_done_clock: optional int64 device tensor [n_evt] that receives the
-        device clock at each event record's write."""
+        device clock at each event record's write; tel_class: optional float32
+        device tensor [n_tel][2] that receives each telescope's gamma score and
+        log10 E, classified in the reconstruction kernel (needs attach_mlp)."""
         import torch
         _require(traces, torch.uint16, name="traces")
         _require(tel_type, torch.int32, name="tel_type")
@@ -407,9 +409,11 @@ class Pipeline:
             n_evt = evt_tel_off.numel() - 1
         if evt_done_clock is not None:
             _require(evt_done_clock, torch.int64, (n_evt,), "evt_done_clock")
+        if tel_class is not None:
+            _require(tel_class, torch.float32, (n_tel, 2), "tel_class")
         b = Batch(_ptr(traces), traces.numel(), _ptr(evt_tel_off), _ptr(tel_type), _ptr(tel_trace_off), n_evt, n_tel,
-                  _ptr(evt_done_clock))
-        b._keep = (traces, tel_type, tel_trace_off, evt_tel_off, evt_done_clock)
+                  _ptr(evt_done_clock), _ptr(tel_class))
+        b._keep = (traces, tel_type, tel_trace_off, evt_tel_off, evt_done_clock, tel_class)
         return b
 
     def alloc_outputs(self, batch, device):

@@ -1148,8 +1148,7 @@ __device__ __forceinline__ int islands_phase(const DevCam& c, TelSmem& sm, int n
 // their centred cross products) is accumulated in FP64: times are absolute
 // sample numbers, so FP32 would cancel most digits of small time gradients.
 template <int NT, int W, bool FUSED>
-__device__ __forceinline__ void hillas_phase(const DevCam& c, TelSmem& sm, int n, int roots, int nlow,
-                                             rta_hillas_rec* out) {
+__device__ __forceinline__ rta_hillas_rec hillas_phase(const DevCam& c, TelSmem& sm, int n, int roots, int nlow) {
   float v1[6] = {0.f, 0.f, 0.f, 0.f, (float)roots, (float)nlow};
   for (int j = threadIdx.x; j < n; j += NT) {
     const int i = sm.list[j] & 0x7FFF;
@@ -1171,8 +1170,7 @@ __device__ __forceinline__ void hillas_phase(const DevCam& c, TelSmem& sm, int n
     r.cog_x = r.cog_y = r.length = r.width = r.psi = r.skewness = r.kurtosis = kNaN;
     r.time_gradient = r.time_intercept = r.leakage = r.cog_dist = kNaN;
     r.flags |= RTA_FLAG_HILLAS_INVALID | RTA_FLAG_TIME_INVALID;
-    if (threadIdx.x == 0) *out = r;
-    return;
+    return r;
   }
   const float xm = v1[1] / S, ym = v1[2] / S;
   float v2[3] = {0.f, 0.f, 0.f};
@@ -1233,12 +1231,14 @@ __device__ __forceinline__ void hillas_phase(const DevCam& c, TelSmem& sm, int n
     r.time_gradient = r.time_intercept = kNaN;
     r.flags |= RTA_FLAG_TIME_INVALID;
   }
-  if (threadIdx.x == 0) *out = r;
+  return r;
 }
 
+// Calibration -> cleaning -> Hillas of one camera event; every thread
+// returns the same record.
 template <int EX, int PPL, int W, int CH, int NT>
-__device__ __forceinline__ void process_telescope(const DevCam& c, const uint16_t* __restrict__ ev, TelSmem& sm,
-                                                  rta_hillas_rec* out) {
+__device__ __forceinline__ rta_hillas_rec process_telescope(const DevCam& c, const uint16_t* __restrict__ ev,
+                                                            TelSmem& sm) {
   const int nlow = extract_phase<EX, PPL, W, CH, NT>(c, ev, sm);
   __syncthreads();
   mask_phase<NT>(c, sm);
@@ -1249,7 +1249,7 @@ __device__ __forceinline__ void process_telescope(const DevCam& c, const uint16_
   list_phase<NT, W, true>(c, sm, ev, nullptr, nullptr, nullptr);
   __syncthreads();
   const int roots = islands_phase<NT>(c, sm, n);
-  hillas_phase<NT, W, true>(c, sm, n, roots, nlow, out);
+  return hillas_phase<NT, W, true>(c, sm, n, roots, nlow);
 }
 
 __device__ __forceinline__ void bad_record(rta_hillas_rec* out) {
@@ -1371,11 +1371,54 @@ __global__ __launch_bounds__(NT) void k_hillas(DevCam c, const int32_t* __restri
   list_phase<NT, W, false>(c, sm, nullptr, D + ob, gain ? gain + ob : nullptr, t + ob);
   __syncthreads();
   const int roots = islands_phase<NT>(c, sm, n);
-  hillas_phase<NT, W, false>(c, sm, n, roots, nlow, out + e);
+  const rta_hillas_rec r = hillas_phase<NT, W, false>(c, sm, n, roots, nlow);
+  if (threadIdx.x == 0) out[e] = r;
 }
 
 __global__ void k_queue_reset(unsigned long long* q) {
   if (threadIdx.x == 0) *q = 0ull;
+}
+
+// Classification of one telescope right after its Hillas parameters, by the
+// first wavefront: the record is row 0 of a 16-row network tile (the other
+// rows zero; a tile's rows do not affect each other, so the outputs equal
+// those of the same record in any other tile), then the network-or-box-cut
+// decision.  Lane 0 writes the score and log10 E and marks the fallback in
+// the record; records without a valid image get NaN.  (Spreading the four
+// tiles of each layer over four wavefronts, with the activations exchanged
+// through LDS, was no faster: the layers wait on their weight loads.)
+__device__ __forceinline__ void classify_telescope(const FusedArgs& a, long long tel, rta_hillas_rec& r) {
+  const int lane = threadIdx.x & (kWave - 1), col = lane & 15, grp = lane >> 4;
+  const bool valid = !(r.flags & RTA_FLAG_HILLAS_INVALID);
+  float logit = 0.f, me = 0.f;
+  if (valid && a.have_mlp) {  // uniform over the wavefront
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (col == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int f = 4 * grp + j;
+        if (f < mlpdev::kIn) {
+          const float z = (mlpdev::record_feature(r, f) - a.mlp.mean[f]) / a.mlp.stdv[f];
+          v[j] = isfinite(z) ? z : 0.f;
+        }
+      }
+    }
+    mlpdev::bf16x4 h1[4], h2[4], h3[4];
+    const mlpdev::f32x4 o = mlpdev::mlp_forward_tile(a.mlp, mlpdev::pack4(v[0], v[1], v[2], v[3]), h1, h2, h3);
+    logit = o[0];
+    me = o[1];
+  }
+  if (lane == 0) {
+    float score = kNaN, log10e = kNaN;
+    if (valid) {
+      const mlpdev::ClassOut co = mlpdev::classify_record(r, a.bc, a.have_mlp != 0, logit, me);
+      if (co.fallback) r.flags |= RTA_FLAG_MLP_FALLBACK;
+      score = co.score;
+      log10e = co.log10e;
+    }
+    a.tel_class[2 * tel] = score;
+    a.tel_class[2 * tel + 1] = log10e;
+  }
 }
 
 // Per-telescope body of the fused kernel: descriptor checks, then
@@ -1389,11 +1432,17 @@ __device__ __forceinline__ void fused_telescope(const FusedArgs& a, long long te
   if (bad) {
     if (threadIdx.x == 0) {
       bad_record(a.out + tel);
+      if (a.classify) {
+        a.tel_class[2 * tel] = kNaN;
+        a.tel_class[2 * tel + 1] = kNaN;
+      }
       atomicOr(a.status, bad);
     }
     return;
   }
-  process_telescope<EX, PPL, W, CH, NT>(a.cams[ty], uniform_ptr(a.traces + off), sm, a.out + tel);
+  rta_hillas_rec r = process_telescope<EX, PPL, W, CH, NT>(a.cams[ty], uniform_ptr(a.traces + off), sm);
+  if (a.classify && threadIdx.x < kWave) classify_telescope(a, tel, r);
+  if (threadIdx.x == 0) a.out[tel] = r;
 }
 
 // Persistent form: a fixed grid of workgroups pulls telescopes from a global
@@ -1478,7 +1527,7 @@ __global__ __launch_bounds__(kEvtNT) void k_event(EventArgs a) {
     const int col = lane & 15, grp = lane >> 4;
     for (int64_t r0 = lo; r0 < hi; r0 += 16) {
       float logit = 0.f, me = 0.f;
-      if (a.have_mlp) {
+      if (a.have_mlp && !a.tel_class) {
         mlpdev::bf16x4 h1[4], h2[4], h3[4];
         const mlpdev::bf16x4 xin = mlpdev::mlp_record_tile(a.mlp, a.tel, hi, r0);
         const mlpdev::f32x4 o = mlpdev::mlp_forward_tile(a.mlp, xin, h1, h2, h3);
@@ -1490,11 +1539,19 @@ __global__ __launch_bounds__(kEvtNT) void k_event(EventArgs a) {
         rta_hillas_rec h = a.tel[k];
         const int ty = a.tel_type[k];
         if (ty >= 0 && ty < a.n_types && !(h.flags & (RTA_FLAG_HILLAS_INVALID | RTA_FLAG_BAD_DESCRIPTOR))) {
-          const mlpdev::ClassOut co = mlpdev::classify_record(h, a.bc, a.have_mlp != 0, logit, me);
-          if (co.fallback) a.tel[k].flags = h.flags | RTA_FLAG_MLP_FALLBACK;
-          if (isfinite(co.log10e) && h.size > 0.f) {
-            c[0] += h.size * co.score;
-            c[1] += h.size * co.log10e;
+          float score, log10e;
+          if (a.tel_class) {  // classified in the reconstruction kernel
+            score = a.tel_class[2 * k];
+            log10e = a.tel_class[2 * k + 1];
+          } else {
+            const mlpdev::ClassOut co = mlpdev::classify_record(h, a.bc, a.have_mlp != 0, logit, me);
+            if (co.fallback) a.tel[k].flags = h.flags | RTA_FLAG_MLP_FALLBACK;
+            score = co.score;
+            log10e = co.log10e;
+          }
+          if (isfinite(log10e) && h.size > 0.f) {
+            c[0] += h.size * score;
+            c[1] += h.size * log10e;
             c[2] += h.size;
           }
         }

@@ -179,6 +179,13 @@ rta_status launch_batch(const rta_pipeline* pipe, const rta_batch* b, rta_hillas
   fa.out = tel_out;
   fa.queue = queue;
   fa.status = status;
+  if (b->tel_class && pipe->have_box) {
+    fa.classify = 1;
+    fa.tel_class = b->tel_class;
+    fa.bc = pipe->bc;
+    fa.have_mlp = pipe->mlp ? 1 : 0;
+    if (pipe->mlp) fa.mlp = pipe->mlp->dev;
+  }
   if (b->n_tel > 0) {
     RTA_HIP(rta::launch_queue_reset(queue, st));
     RTA_HIP(rta::launch_fused(fa, pipe->sched, pipe->n_cu, st));
@@ -192,6 +199,7 @@ rta_status launch_batch(const rta_pipeline* pipe, const rta_batch* b, rta_hillas
     ea.n_tel = b->n_tel;
     ea.tel = tel_out;
     ea.out = evt_out;
+    ea.tel_class = fa.classify ? b->tel_class : nullptr;
     ea.done_clock = b->evt_done_clock;
     ea.status = status;
     RTA_HIP(rta::launch_event(ea, st));
@@ -208,6 +216,8 @@ rta_status check_batch(const rta_pipeline* pipe, const rta_batch* b, const rta_h
       return fail(RTA_E_INVALID_ARG, "null trace pool, descriptor or output pointer");
     if (!aligned16(b->traces)) return fail(RTA_E_INVALID_ARG, "trace pool must be 16-byte aligned");
   }
+  if (b->tel_class && !pipe->have_box)
+    return fail(RTA_E_INVALID_ARG, "tel_class needs a classifier attached to the pipeline");
   if (pipe->params.do_stereo && b->n_evt > 0) {
     if (!b->evt_tel_off || !evt_out || !tel_out) return fail(RTA_E_INVALID_ARG, "null event offsets or output");
     if ((int64_t)(b->n_evt + 3) / 4 > 0x7fffffffLL) return fail(RTA_E_SHAPE, "too many events for one launch");

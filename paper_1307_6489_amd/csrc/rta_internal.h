@@ -85,6 +85,13 @@ struct FusedArgs {
   rta_hillas_rec* out;
   unsigned long long* queue;
   uint32_t* status;
+  // classification after Hillas (classify != 0): network (have_mlp) and box
+  // cuts, per-telescope [score, log10 E] to tel_class
+  int32_t classify;
+  int32_t have_mlp;
+  float* tel_class;
+  MlpDev mlp;
+  rta_boxcut_desc bc;
 };
 
 struct DecodeArgs {
@@ -130,6 +137,7 @@ struct EventArgs {
   int64_t n_tel;
   rta_hillas_rec* tel;
   rta_event_rec* out;
+  const float* tel_class; // [n_tel][2] or null: telescopes already classified
   uint64_t* done_clock;   // [n_evt] or null: device clock at each record write
   uint32_t* status;
 };

@@ -181,7 +181,8 @@ def clock_pair(stream=None):
     return best
 
 
-def paced_latency(pipe, ps: PinnedArrayStream, rate_GBps, n_chunks, dev, warmup=4, keep_records=False):
+def paced_latency(pipe, ps: PinnedArrayStream, rate_GBps, n_chunks, dev, warmup=4, keep_records=False,
+                  classify_after_hillas=False):
     """Submit ``n_chunks`` chunks (cycling through the pinned array events) at
     the paced DL0 rate: a chunk arrives on the host clock when its last byte
     would have arrived at ``rate_GBps``, and is then copied on a copy stream
@@ -193,7 +194,10 @@ def paced_latency(pipe, ps: PinnedArrayStream, rate_GBps, n_chunks, dev, warmup=
     before and after the run, minus the chunk's arrival (this includes any
     wait behind earlier copies).  p50 / p99 over every array event of the
     timed chunks.  keep_records: also the device records of each chunk's last
-    pass ("records": [(tel, evt)] per chunk of the stream)."""
+    pass ("records": [(tel, evt)] per chunk of the stream).
+    classify_after_hillas: with a classifier attached, each telescope is
+    classified in the reconstruction kernel (per-telescope scores to a
+    tel_class buffer per chunk) rather than in the per-event pass."""
     import torch
     copy_s, comp_s = torch.cuda.Stream(), torch.cuda.Stream()
     nbuf = 3
@@ -205,7 +209,8 @@ def paced_latency(pipe, ps: PinnedArrayStream, rate_GBps, n_chunks, dev, warmup=
         eo = torch.from_numpy((ps.evt_tel_off[e_lo:e_hi + 1] - t_lo).astype(np.int64)).to(dev)
         tel = torch.empty((t_hi - t_lo, 16), dtype=torch.float32, device=dev)
         evt = torch.empty((e_hi - e_lo, 8), dtype=torch.float32, device=dev)
-        descs.append((ty, off, eo, tel, evt))
+        cls = torch.empty((t_hi - t_lo, 2), dtype=torch.float32, device=dev) if classify_after_hillas else None
+        descs.append((ty, off, eo, tel, evt, cls))
     n_inst = n_chunks + warmup
     inst = [i % len(ps.chunks) for i in range(n_inst)]
     n_ev_inst = np.array([ps.chunks[c][3] - ps.chunks[c][2] for c in inst], np.int64)
@@ -239,8 +244,9 @@ def paced_latency(pipe, ps: PinnedArrayStream, rate_GBps, n_chunks, dev, warmup=
         rta.device_stamp(h2d_clock[i:i + 1], copy_s)
         copied[i].record(copy_s)
         comp_s.wait_event(copied[i])
-        ty, off, eo, tel, evt = descs[c]
-        bt = pipe.make_batch(bufs[b], ty, off, eo, evt_done_clock=done_clock[ev_base[i]:ev_base[i + 1]])
+        ty, off, eo, tel, evt, cls = descs[c]
+        bt = pipe.make_batch(bufs[b], ty, off, eo, evt_done_clock=done_clock[ev_base[i]:ev_base[i + 1]],
+                             tel_class=cls)
         pipe.process(bt, tel, evt, stream=comp_s)
         freed[b].record(comp_s)
         if i >= warmup:

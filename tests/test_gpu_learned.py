@@ -161,6 +161,58 @@ def test_event_pass_with_network(dev, small_model):
         assert np.array_equal(fbk[ok], c[ok, 3] > 0.5)
 
 
+def test_classification_fused_after_hillas(dev, small_model):
+    """Array events with the network attached, each telescope classified in
+    the reconstruction kernel right after its Hillas parameters (tel_class
+    given): scores and log10 E bit-identical to rta_classify on the same
+    records, the same fallback flags, NaN for telescopes without a valid
+    image, and every telescope and event record byte-identical to the run
+    that classifies in the per-event pass; without stereo the same values."""
+    import torch
+    cam_c0, tr, te, net, bc, info = small_model
+    aw = W.array_events(20, seed=8)
+    cams = [rta.Camera.from_type(c) for c in aw.pool.cams]
+    blob = torch.from_numpy(aw.pool.blob).to(dev)
+    ty, off = torch.from_numpy(aw.tel_type).to(dev), torch.from_numpy(aw.tel_off).to(dev)
+    eo = torch.from_numpy(aw.evt_tel_off).to(dev)
+    n_tel = len(aw.tel_type)
+    pipe = rta.Pipeline(cams, do_stereo=True)
+    pipe.attach_mlp(net, bc)
+    b1 = pipe.make_batch(blob, ty, off, eo)
+    tel1, evt1 = pipe.alloc_outputs(b1, dev)
+    pipe.process(b1, tel1, evt1)
+    cls = torch.full((n_tel, 2), -7.0, dtype=torch.float32, device=dev)
+    b2 = pipe.make_batch(blob, ty, off, eo, tel_class=cls)
+    tel2, evt2 = pipe.alloc_outputs(b2, dev)
+    pipe.process(b2, tel2, evt2)
+    torch.cuda.synchronize()
+    assert pipe.status() == 0
+    assert torch.equal(tel1.view(torch.int32), tel2.view(torch.int32))
+    assert torch.equal(evt1.view(torch.int32), evt2.view(torch.int32))
+    rec = rta.records(tel2)
+    ref = rta.classify(net, bc, tel2).cpu().numpy()
+    c = cls.cpu().numpy()
+    valid = (rec["flags"] & rta.FLAG_HILLAS_INVALID) == 0
+    assert valid.sum() > 100 and (~valid).sum() > 0
+    assert np.array_equal(c[valid].view(np.int32), ref[valid, :2].view(np.int32))
+    assert np.all(np.isnan(c[~valid]))
+    fb = (rec["flags"] & rta.FLAG_MLP_FALLBACK) > 0
+    assert np.array_equal(fb[valid], ref[valid, 3] > 0.5) and not fb[~valid].any()
+    # per-telescope classification without the per-event pass
+    pipe_ns = rta.Pipeline(cams, do_stereo=False)
+    pipe_ns.attach_mlp(net, bc)
+    cls3 = torch.full((n_tel, 2), -7.0, dtype=torch.float32, device=dev)
+    b3 = pipe_ns.make_batch(blob, ty, off, tel_class=cls3)
+    tel3, _ = pipe_ns.alloc_outputs(b3, dev)
+    pipe_ns.process(b3, tel3)
+    torch.cuda.synchronize()
+    assert torch.equal(cls3.view(torch.int32), cls.view(torch.int32))
+    assert torch.equal(tel3.view(torch.int32), tel2.view(torch.int32))
+    with pytest.raises(rta.RTAError):
+        bare = rta.Pipeline(cams, do_stereo=False)
+        bare.process(bare.make_batch(blob, ty, off, tel_class=cls3), tel3)
+
+
 def test_network_beats_box_cuts(dev, small_model):
     """At equal gamma efficiency on the held-out seed the network accepts
     fewer hadrons than the scaled-width/length box cuts (by more than three
