@@ -1142,11 +1142,14 @@ __device__ __forceinline__ int islands_phase(const DevCam& c, TelSmem& sm, int n
 
 // Phase 6: Hillas reductions and the record.
 // Centre of gravity and second moments are FP32 sums of centred terms.  The
-// width comes from the minor-axis moment taken in the rotated frame (exact
-// for collinear pixels, unlike sqrt(det / l+), which keeps only half the
-// digits when the width is small).  The time regression (sums of l and t,
-// their centred cross products) is accumulated in FP64: times are absolute
-// sample numbers, so FP32 would cancel most digits of small time gradients.
+// third pass takes the longitudinal and transverse coordinates l, w in the
+// rotated frame: skewness and kurtosis from q l^3, q l^4, the width from the
+// minor-axis moment q w^2 (exact for collinear pixels, unlike
+// sqrt(det / l+), which keeps only half the digits when the width is small),
+// and the time regression from the FP64 sums of l, l^2, t and l t (times are
+// absolute sample numbers, so FP32 would cancel most digits of small time
+// gradients; in FP64 the centring cancels about t / spread(t) x mean(l) /
+// spread(l) digits, harmless).
 template <int NT, int W, bool FUSED>
 __device__ __forceinline__ rta_hillas_rec hillas_phase(const DevCam& c, TelSmem& sm, int n, int roots, int nlow) {
   float v1[6] = {0.f, 0.f, 0.f, 0.f, (float)roots, (float)nlow};
@@ -1189,7 +1192,15 @@ __device__ __forceinline__ rta_hillas_rec hillas_phase(const DevCam& c, TelSmem&
   if (psi <= -0.5f * (float)M_PI) psi += (float)M_PI;
   const float len = sqrtf(lp);
   const float cs = cosf(psi), sn = sinf(psi);
-  double v3[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // q l^3, q l^4, q w^2, l, t
+  // l of slot 0: every l equal to it (fewer than two distinct l) leaves the
+  // time gradient undefined
+  float l0;
+  {
+    const int i = sm.list[0] & 0x7FFF;
+    l0 = (c.x[i] - xm) * cs + (c.y[i] - ym) * sn;
+  }
+  // q l^3, q l^4, q w^2, l, l^2, t, l t, |l - l0|
+  double v3[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int j = threadIdx.x; j < n; j += NT) {
     const int i = sm.list[j] & 0x7FFF;
     const float q = slot_q<FUSED>(c, sm, j, i), dx = c.x[i] - xm, dy = c.y[i] - ym;
@@ -1199,20 +1210,16 @@ __device__ __forceinline__ rta_hillas_rec hillas_phase(const DevCam& c, TelSmem&
     v3[0] += (double)(q * l2 * l);
     v3[1] += (double)(q * l2 * l2);
     v3[2] += (double)(q * w * w);
-    v3[3] += (double)l;
-    v3[4] += slot_t<FUSED, W>(sm, j);
+    const double ld = (double)l, td = slot_t<FUSED, W>(sm, j);
+    v3[3] += ld;
+    v3[4] += ld * ld;
+    v3[5] += td;
+    v3[6] += ld * td;
+    v3[7] += fabs(ld - (double)l0);
   }
-  block_sum<double, 5, NT>(v3, sm.red);
-  const double lbar = v3[3] / (double)n, tbar = v3[4] / (double)n;
-  double v4[2] = {0.0, 0.0};
-  for (int j = threadIdx.x; j < n; j += NT) {
-    const int i = sm.list[j] & 0x7FFF;
-    const float dx = c.x[i] - xm, dy = c.y[i] - ym;
-    const double l = (double)(dx * cs + dy * sn) - lbar;
-    v4[0] += l * l;
-    v4[1] += l * (slot_t<FUSED, W>(sm, j) - tbar);
-  }
-  block_sum<double, 2, NT>(v4, sm.red);
+  block_sum<double, 8, NT>(v3, sm.red);
+  const double nd = (double)n, lbar = v3[3] / nd, tbar = v3[5] / nd;
+  const double sll = v3[4] - v3[3] * lbar, slt = v3[6] - v3[3] * tbar;
   r.cog_x = xm;
   r.cog_y = ym;
   r.length = len;
@@ -1223,8 +1230,8 @@ __device__ __forceinline__ rta_hillas_rec hillas_phase(const DevCam& c, TelSmem&
   r.kurtosis = (float)v3[1] / (S * len3 * len);
   r.leakage = v1[3] / S;
   r.cog_dist = sqrtf(xm * xm + ym * ym);
-  if (v4[0] > 0.0) {
-    const double g = v4[1] / v4[0];
+  if (v3[7] > 0.0 && sll > 0.0) {
+    const double g = slt / sll;
     r.time_gradient = (float)g;
     r.time_intercept = (float)(tbar - g * lbar);
   } else {
