@@ -98,7 +98,8 @@ typedef enum rta_status {
   RTA_E_SHAPE = 2,        /* unsupported size: N > RTA_MAX_PIX, T > RTA_MAX_SAMP, window not compiled */
   RTA_E_HIP = 3,          /* a HIP runtime call failed (message in rta_last_error) */
   RTA_E_NOMEM = 4,        /* device or host allocation for a handle failed */
-  RTA_E_UNSUPPORTED = 5   /* schedule or option not available */
+  RTA_E_UNSUPPORTED = 5,  /* schedule or option not available */
+  RTA_E_UNTUNED = 6       /* the tune cache holds no schedule for this pipeline's key */
 } rta_status;
 
 /* record flag bits (rta_hillas_rec.flags) */
@@ -192,6 +193,14 @@ typedef struct rta_pipeline_params {
                                run one workgroup per telescope (wg_per_cu ignored) */
   float max_width_ratio;    /* stereo: drop images with width/length above (0.9) */
   float max_cond;           /* stereo: invalid at condition number >= this (1e4) */
+  const char* tune_cache;   /* NULLABLE path of a schedule tune cache (read at creation, copied):
+                               NULL runs the default schedule.  Otherwise the pipeline takes
+                               the schedule the cache holds for its tune key; if the file has no
+                               such entry (or does not exist), rta_process_batch,
+                               rta_process_batch_noalloc and rta_graph_capture return
+                               RTA_E_UNTUNED until rta_pipeline_tune or rta_set_schedule has
+                               set a schedule, and rta_pipeline_tune records its result in
+                               this file. */
 } rta_pipeline_params;
 
 /* Launch schedule of the fused kernel (chosen by the autotuner).  A new
@@ -291,6 +300,44 @@ rta_status rta_process_batch(rta_pipeline* pipe, const rta_batch* batch, rta_hil
 #define RTA_NOALLOC_SCRATCH_BYTES 256
 rta_status rta_process_batch_noalloc(const rta_pipeline* pipe, const rta_batch* batch, rta_hillas_rec* tel_out,
                                      rta_event_rec* evt_out, uint32_t* status_out, rta_stream stream);
+
+/* Schedule tuning.  A launch-configuration search, not a step of the
+ * reconstruction: records and statuses are the same under every schedule.
+ *
+ * Tune key of a pipeline: "<arch>|e<extractor>w<window>|<N>x<T>x<G>;..." over
+ * its camera types in order, arch being the device's gfx name ("gfx950").
+ * key: host buffer of cap bytes (RTA_TUNE_KEY_MAX suffices); RTA_E_INVALID_ARG
+ * if it does not fit. */
+#define RTA_TUNE_KEY_MAX 512
+rta_status rta_pipeline_tune_key(const rta_pipeline* pipe, char* key, int32_t cap);
+
+/* Times candidate schedules of the fused path on one batch and applies the
+ * fastest.  Each candidate runs one untimed rta_process_batch, then reps
+ * (1..100) timed ones bracketed by HIP events on stream; its time is the
+ * median.  cands: NULLABLE host array of n_cands schedules (all must be
+ * compiled, else RTA_E_UNSUPPORTED before any launch); NULL times every
+ * compiled schedule (rta_list_schedules) and ignores n_cands.  ms: NULLABLE
+ * host array, one median per candidate in milliseconds.  best: NULLABLE,
+ * receives the chosen schedule.  Batch, outputs and validation as for
+ * rta_process_batch (the outputs hold the last run's records afterwards).
+ * Synchronises the stream.  If the pipeline was created with a tune cache, the
+ * result is stored there under the pipeline's key (replacing an older entry;
+ * an unwritable file gives RTA_E_INVALID_ARG after the schedule is applied).
+ * On a failed launch the previous schedule is kept. */
+rta_status rta_pipeline_tune(rta_pipeline* pipe, const rta_batch* batch, rta_hillas_rec* tel_out,
+                             rta_event_rec* evt_out, const rta_schedule* cands, int32_t n_cands, int32_t reps,
+                             float* ms, rta_schedule* best, rta_stream stream);
+
+/* The tune cache file: UTF-8 text, one entry per line,
+ * "<key>\t<pix_per_lane> <waves_per_wg> <wg_per_cu> <chunk>\t<ms>"; lines
+ * starting with '#' and lines that do not parse are ignored.  Host-only calls
+ * (no GPU use).  Lookup: RTA_E_UNTUNED when the file is missing or holds no
+ * parseable entry for key, or when the entry's schedule is not compiled into
+ * this library; ms NULLABLE.  Store: replaces the key's entry (or appends one)
+ * and rewrites the file through a temporary file renamed over it, so readers
+ * see the old or the new file; keys may not hold tabs or line breaks. */
+rta_status rta_tune_cache_lookup(const char* path, const char* key, rta_schedule* s, float* ms);
+rta_status rta_tune_cache_store(const char* path, const char* key, const rta_schedule* s, float ms);
 
 /* Stereo per array event from existing telescope records, using the
  * pipeline's focal lengths and cuts.  evt_tel_off [n_evt+1] (values in

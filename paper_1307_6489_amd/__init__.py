@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_PKG, "librta.so")
 
 RTA_OK = 0
 STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "unsupported shape", 3: "HIP runtime error",
-                4: "out of memory", 5: "unsupported option"}
+                4: "out of memory", 5: "unsupported option", 6: "no tuned schedule"}
+RTA_E_UNTUNED = 6
 EXTRACT_SLIDING = 0       # per pixel: earliest maximiser of the window sum
 EXTRACT_FIXED = 1         # every pixel: the camera's fixed window start
 EXTRACT_GLOBAL_PEAK = 2   # every pixel: earliest maximiser of the camera-summed window
@@ -70,7 +71,7 @@ class Batch(ctypes.Structure):
 
 class PipelineParams(ctypes.Structure):
     _fields_ = [("do_stereo", ctypes.c_int32), ("extractor", ctypes.c_int32), ("max_width_ratio", ctypes.c_float),
-                ("max_cond", ctypes.c_float)]
+                ("max_cond", ctypes.c_float), ("tune_cache", ctypes.c_char_p)]
 
 
 class Schedule(ctypes.Structure):
@@ -135,6 +136,10 @@ SYMBOLS = {
     "rta_set_schedule": ([_vp, _vp], ctypes.c_int),
     "rta_get_schedule": ([_vp, _vp], ctypes.c_int),
     "rta_list_schedules": ([_vp, _i32, _vp], ctypes.c_int),
+    "rta_pipeline_tune_key": ([_vp, ctypes.c_char_p, _i32], ctypes.c_int),
+    "rta_pipeline_tune": ([_vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp], ctypes.c_int),
+    "rta_tune_cache_lookup": ([ctypes.c_char_p, ctypes.c_char_p, _vp, _vp], ctypes.c_int),
+    "rta_tune_cache_store": ([ctypes.c_char_p, ctypes.c_char_p, _vp, ctypes.c_float], ctypes.c_int),
     "rta_process_batch": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "rta_process_batch_noalloc": ([_vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "rta_stereo": ([_vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
@@ -264,6 +269,26 @@ def list_schedules():
     return [s.as_tuple() for s in arr]
 
 
+TUNE_KEY_MAX = 512
+
+
+def tune_cache_lookup(path, key):
+    """(schedule tuple, ms) the tune cache file holds for key, or None
+    (no file, no entry, or a schedule this library does not compile)."""
+    s, ms = Schedule(), ctypes.c_float()
+    st = lib().rta_tune_cache_lookup(os.fsencode(path), key.encode(), ctypes.byref(s), ctypes.byref(ms))
+    if st == RTA_E_UNTUNED:
+        return None
+    _check(st)
+    return s.as_tuple(), ms.value
+
+
+def tune_cache_store(path, key, sched, ms):
+    """Record sched (4-tuple) with its time for key in the tune cache file."""
+    s = Schedule(*sched)
+    _check(lib().rta_tune_cache_store(os.fsencode(path), key.encode(), ctypes.byref(s), float(ms)))
+
+
 class Camera:
     """A camera type on the current device (pedestals in Q8, integer cleaning
     thresholds, neighbour table)."""
@@ -365,10 +390,14 @@ def records(t, dtype=HILLAS_DTYPE):
 class Pipeline:
     """Fused batched path over several camera types."""
 
-    def __init__(self, cams, do_stereo=True, max_width_ratio=0.9, max_cond=1e4, extractor=0):
+    def __init__(self, cams, do_stereo=True, max_width_ratio=0.9, max_cond=1e4, extractor=0, tune_cache=None):
+        """tune_cache: optional path of a schedule tune cache.  With one, the
+        pipeline takes the cached schedule for its key, or refuses to process
+        (RTAError status RTA_E_UNTUNED) until tune() or set_schedule()."""
         self.cams = list(cams)
         arr = (ctypes.c_void_p * len(self.cams))(*[c.handle.value for c in self.cams])
-        p = PipelineParams(1 if do_stereo else 0, int(extractor), max_width_ratio, max_cond)
+        p = PipelineParams(1 if do_stereo else 0, int(extractor), max_width_ratio, max_cond,
+                           None if tune_cache is None else os.fsencode(tune_cache))
         self.extractor = int(extractor)
         h = ctypes.c_void_p()
         _check(lib().rta_pipeline_create(arr, len(self.cams), ctypes.byref(p), ctypes.byref(h)))
@@ -389,6 +418,23 @@ class Pipeline:
         s = Schedule()
         _check(lib().rta_get_schedule(self.handle, ctypes.byref(s)))
         return s.as_tuple()
+
+    def tune_key(self):
+        buf = ctypes.create_string_buffer(TUNE_KEY_MAX)
+        _check(lib().rta_pipeline_tune_key(self.handle, buf, TUNE_KEY_MAX))
+        return buf.value.decode()
+
+    def tune(self, batch, tel_out, evt_out=None, candidates=None, reps=3, stream=None):
+        """rta_pipeline_tune: time candidate schedules (all compiled ones by
+        default) on batch, apply the fastest, store it in the pipeline's tune
+        cache if it has one.  Returns (best tuple, {schedule: median ms})."""
+        cands = list(candidates) if candidates is not None else list_schedules()
+        arr = (Schedule * len(cands))(*[Schedule(*c) for c in cands])
+        ms = (ctypes.c_float * len(cands))()
+        best = Schedule()
+        _check(lib().rta_pipeline_tune(self.handle, ctypes.byref(batch), _ptr(tel_out), _ptr(evt_out), arr,
+                                       len(cands), int(reps), ms, ctypes.byref(best), _stream(stream)))
+        return best.as_tuple(), {tuple(c): ms[i] for i, c in enumerate(cands)}
 
     @staticmethod
     def make_batch(traces, tel_type, tel_trace_off, evt_tel_off=None, evt_done_clock=None, tel_class=None):

@@ -1,5 +1,8 @@
 // C ABI of librta: argument validation, camera tables, pipelines, graphs.
+#include <unistd.h>
+
 #include <algorithm>
+#include <cerrno>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -34,6 +37,9 @@ struct rta_pipeline {
   unsigned long long* d_queue = nullptr;  // work-queue counter
   uint32_t* d_status = nullptr;           // RTA_STATUS_* bits
   hipStream_t capture_stream = nullptr;
+  std::string tune_key;                   // "<arch>|e<extractor>w<window>|<N>x<T>x<G>;..."
+  std::string tune_cache;                 // tune cache path ("" without one)
+  bool untuned = false;                   // a cache was given but held no schedule yet
 };
 
 struct rta_sam {
@@ -207,9 +213,69 @@ rta_status launch_batch(const rta_pipeline* pipe, const rta_batch* b, rta_hillas
   return RTA_OK;
 }
 
+// ---- schedule tune cache (text file, one "<key>\t<4 ints>\t<ms>" line per key)
+
+std::mutex g_tune_file_mu;  // serialises read-modify-write of cache files within the process
+
+bool parse_tune_line(const std::string& line, std::string* key, rta_schedule* s, float* ms) {
+  if (line.empty() || line[0] == '#') return false;
+  const size_t tab = line.find('\t');
+  if (tab == std::string::npos || tab == 0) return false;
+  rta_schedule v{};
+  float t = 0.f;
+  char extra = 0;
+  if (std::sscanf(line.c_str() + tab + 1, " %d %d %d %d %f %c", &v.pix_per_lane, &v.waves_per_wg, &v.wg_per_cu,
+                  &v.chunk, &t, &extra) != 5)
+    return false;
+  *key = line.substr(0, tab);
+  *s = v;
+  *ms = t;
+  return true;
+}
+
+// Lines of a text file without their line breaks; false if it cannot be opened.
+bool read_lines(const char* path, std::vector<std::string>* lines) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  std::string cur;
+  char buf[1024];
+  while (std::fgets(buf, sizeof(buf), f)) {
+    cur += buf;
+    if (!cur.empty() && cur.back() == '\n') {
+      cur.pop_back();
+      if (!cur.empty() && cur.back() == '\r') cur.pop_back();
+      lines->push_back(cur);
+      cur.clear();
+    }
+  }
+  if (!cur.empty()) lines->push_back(cur);
+  std::fclose(f);
+  return true;
+}
+
+rta_status make_tune_key(const rta_pipeline* p, std::string* key) {
+  hipDeviceProp_t prop;
+  RTA_HIP(hipGetDeviceProperties(&prop, p->device));
+  std::string arch(prop.gcnArchName);
+  arch = arch.substr(0, arch.find(':'));
+  char buf[64];
+  std::snprintf(buf, sizeof(buf), "|e%dw%d|", (int)p->params.extractor, p->window);
+  std::string k = arch + buf;
+  for (size_t i = 0; i < p->cams.size(); ++i) {
+    const rta_camera_info& c = p->cams[i]->info;
+    std::snprintf(buf, sizeof(buf), "%s%dx%dx%d", i ? ";" : "", (int)c.n_pix, (int)c.n_samp, (int)c.n_gain);
+    k += buf;
+  }
+  *key = k;
+  return RTA_OK;
+}
+
 rta_status check_batch(const rta_pipeline* pipe, const rta_batch* b, const rta_hillas_rec* tel_out,
-                       const rta_event_rec* evt_out) {
+                       const rta_event_rec* evt_out, bool need_schedule = true) {
   if (!pipe || !b) return fail(RTA_E_INVALID_ARG, "null pipeline or batch");
+  if (need_schedule && pipe->untuned)
+    return fail(RTA_E_UNTUNED, "the tune cache holds no schedule for " + pipe->tune_key +
+                                   "; run rta_pipeline_tune or set a schedule");
   if (b->n_tel < 0 || b->n_evt < 0 || b->traces_len < 0) return fail(RTA_E_INVALID_ARG, "negative batch size");
   if (b->n_tel > 0) {
     if (!b->traces || !b->tel_type || !b->tel_trace_off || !tel_out)
@@ -237,6 +303,7 @@ const char* rta_status_str(rta_status s) {
     case RTA_E_HIP: return "HIP runtime error";
     case RTA_E_NOMEM: return "out of memory";
     case RTA_E_UNSUPPORTED: return "unsupported option";
+    case RTA_E_UNTUNED: return "no tuned schedule";
   }
   return "unknown status";
 }
@@ -478,6 +545,21 @@ rta_status rta_pipeline_create(rta_camera* const* cams, int32_t n_types, const r
     delete p;
     return fail(RTA_E_HIP, "pipeline initialisation failed");
   }
+  p->params.tune_cache = nullptr;  // the caller's string is not kept
+  rta_status ks = make_tune_key(p, &p->tune_key);
+  if (ks != RTA_OK) {
+    (void)rta_pipeline_destroy(p);
+    return ks;
+  }
+  if (params->tune_cache) {
+    p->tune_cache = params->tune_cache;
+    rta_schedule cached{};
+    if (rta_tune_cache_lookup(params->tune_cache, p->tune_key.c_str(), &cached, nullptr) == RTA_OK)
+      p->sched = cached;
+    else
+      p->untuned = true;
+    g_err.clear();
+  }
   *out = p;
   return RTA_OK;
 }
@@ -495,6 +577,7 @@ rta_status rta_set_schedule(rta_pipeline* p, const rta_schedule* s) {
   if (!p || !s) return fail(RTA_E_INVALID_ARG, "null pipeline or schedule");
   if (!rta::schedule_supported(*s)) return fail(RTA_E_UNSUPPORTED, "schedule not compiled");
   p->sched = *s;
+  p->untuned = false;
   return RTA_OK;
 }
 
@@ -507,6 +590,125 @@ rta_status rta_get_schedule(const rta_pipeline* p, rta_schedule* s) {
 rta_status rta_list_schedules(rta_schedule* out, int32_t cap, int32_t* n) {
   if (!n || cap < 0 || (cap > 0 && !out)) return fail(RTA_E_INVALID_ARG, "bad schedule list arguments");
   *n = rta::list_schedules(out, cap);
+  return RTA_OK;
+}
+
+rta_status rta_pipeline_tune_key(const rta_pipeline* p, char* key, int32_t cap) {
+  if (!p || !key || cap <= 0) return fail(RTA_E_INVALID_ARG, "null pipeline or key buffer");
+  if ((int64_t)p->tune_key.size() + 1 > cap) return fail(RTA_E_INVALID_ARG, "key buffer too small");
+  std::memcpy(key, p->tune_key.c_str(), p->tune_key.size() + 1);
+  return RTA_OK;
+}
+
+rta_status rta_tune_cache_lookup(const char* path, const char* key, rta_schedule* s, float* ms) {
+  if (!path || !key || !s) return fail(RTA_E_INVALID_ARG, "null path, key or schedule");
+  std::vector<std::string> lines;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_file_mu);
+    if (!read_lines(path, &lines)) return fail(RTA_E_UNTUNED, std::string("no tune cache at ") + path);
+  }
+  std::string k;
+  rta_schedule v{};
+  float t = 0.f;
+  for (const std::string& line : lines) {
+    if (!parse_tune_line(line, &k, &v, &t) || k != key) continue;
+    if (!rta::schedule_supported(v)) return fail(RTA_E_UNTUNED, "cached schedule is not compiled into this library");
+    *s = v;
+    if (ms) *ms = t;
+    return RTA_OK;
+  }
+  return fail(RTA_E_UNTUNED, std::string("no tune cache entry for ") + key);
+}
+
+rta_status rta_tune_cache_store(const char* path, const char* key, const rta_schedule* s, float ms) {
+  if (!path || !key || !s || !*key) return fail(RTA_E_INVALID_ARG, "null path, key or schedule");
+  if (std::strpbrk(key, "\t\r\n")) return fail(RTA_E_INVALID_ARG, "tune keys may not hold tabs or line breaks");
+  if (!rta::schedule_supported(*s)) return fail(RTA_E_UNSUPPORTED, "schedule not compiled");
+  std::lock_guard<std::mutex> lk(g_tune_file_mu);
+  std::vector<std::string> lines, kept;
+  (void)read_lines(path, &lines);  // a missing file starts empty
+  kept.push_back("# rta schedule tune cache: key<TAB>pix_per_lane waves_per_wg wg_per_cu chunk<TAB>ms");
+  std::string k;
+  rta_schedule v{};
+  float t = 0.f;
+  for (const std::string& line : lines)
+    if (parse_tune_line(line, &k, &v, &t) && k != key) kept.push_back(line);
+  char buf[128];
+  std::snprintf(buf, sizeof(buf), "\t%d %d %d %d\t%.6g", (int)s->pix_per_lane, (int)s->waves_per_wg,
+                (int)s->wg_per_cu, (int)s->chunk, (double)ms);
+  kept.push_back(std::string(key) + buf);
+  const std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)getpid());
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return fail(RTA_E_INVALID_ARG, "cannot write " + tmp + ": " + std::strerror(errno));
+  bool ok = true;
+  for (const std::string& line : kept) ok = ok && std::fprintf(f, "%s\n", line.c_str()) > 0;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    const std::string why = std::strerror(errno);
+    (void)std::remove(tmp.c_str());
+    return fail(RTA_E_INVALID_ARG, "cannot write tune cache " + std::string(path) + ": " + why);
+  }
+  return RTA_OK;
+}
+
+rta_status rta_pipeline_tune(rta_pipeline* p, const rta_batch* batch, rta_hillas_rec* tel_out,
+                             rta_event_rec* evt_out, const rta_schedule* cands, int32_t n_cands, int32_t reps,
+                             float* ms, rta_schedule* best, rta_stream stream) {
+  rta_status s = check_batch(p, batch, tel_out, evt_out, false);
+  if (s != RTA_OK) return s;
+  if (reps < 1 || reps > 100) return fail(RTA_E_INVALID_ARG, "reps must be in 1..100");
+  std::vector<rta_schedule> list;
+  if (cands) {
+    if (n_cands < 1) return fail(RTA_E_INVALID_ARG, "need at least one candidate schedule");
+    list.assign(cands, cands + n_cands);
+  } else {
+    list.resize(rta::list_schedules(nullptr, 0));
+    list.resize(rta::list_schedules(list.data(), (int)list.size()));
+  }
+  for (const rta_schedule& c : list)
+    if (!rta::schedule_supported(c)) return fail(RTA_E_UNSUPPORTED, "candidate schedule not compiled");
+  const hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  RTA_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(RTA_E_HIP, "hipEventCreate failed");
+  }
+  const rta_schedule prev = p->sched;
+  std::vector<float> med(list.size(), 0.f), t(reps);
+  rta_status err = RTA_OK;
+  for (size_t i = 0; i < list.size() && err == RTA_OK; ++i) {
+    p->sched = list[i];
+    err = launch_batch(p, batch, tel_out, evt_out, p->d_queue, p->d_status, st);
+    for (int r = 0; r < reps && err == RTA_OK; ++r) {
+      hipError_t e = hipEventRecord(e0, st);
+      if (e == hipSuccess) err = launch_batch(p, batch, tel_out, evt_out, p->d_queue, p->d_status, st);
+      if (e == hipSuccess && err == RTA_OK) e = hipEventRecord(e1, st);
+      if (e == hipSuccess && err == RTA_OK) e = hipEventSynchronize(e1);
+      if (e == hipSuccess && err == RTA_OK) e = hipEventElapsedTime(&t[r], e0, e1);
+      if (e != hipSuccess && err == RTA_OK)
+        err = fail(RTA_E_HIP, std::string("timing a schedule: ") + hipGetErrorString(e));
+    }
+    if (err == RTA_OK) {
+      std::sort(t.begin(), t.end());
+      med[i] = t[reps / 2];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != RTA_OK) {
+    p->sched = prev;
+    return err;
+  }
+  size_t k = 0;
+  for (size_t i = 1; i < list.size(); ++i)
+    if (med[i] < med[k]) k = i;
+  p->sched = list[k];
+  p->untuned = false;
+  if (ms) std::copy(med.begin(), med.end(), ms);
+  if (best) *best = list[k];
+  if (!p->tune_cache.empty())
+    return rta_tune_cache_store(p->tune_cache.c_str(), p->tune_key.c_str(), &list[k], med[k]);
   return RTA_OK;
 }
 
