@@ -69,10 +69,11 @@ def resolution(cams, n_events, dev, seed=31, log=None):
     return out
 
 
-def throughput(pool_n, events, dev, steps=5, log=None):
-    """Fused batch per extractor: camera events / s, kernel time, the bytes
-    each extractor must read (the fixed window reads w samples per pixel;
-    the others the whole high-gain trace) and their rate."""
+def throughput(pool_n, events, dev, steps=5, log=None, only=None):
+    """Fused batch per extractor (only: names to run, default all): camera
+    events / s, kernel time, the bytes each extractor must read (the fixed
+    window reads w samples per pixel; the others the whole high-gain trace)
+    and their rate."""
     import torch
     import dl0sim.workloads as W
     from paper_1307_6489_amd import autotune
@@ -84,6 +85,8 @@ def throughput(pool_n, events, dev, steps=5, log=None):
     stream = torch.cuda.Stream()
     res = {}
     for ex, name in NAMES.items():
+        if only and name not in only:
+            continue
         pipe = rta.Pipeline(cams, do_stereo=False, extractor=ex)
         b = pipe.make_batch(blob, ty_d, off_d)
         tel, _ = pipe.alloc_outputs(b, dev)
@@ -129,12 +132,18 @@ def main():
     ap.add_argument("--events", type=int, default=400, help="events per camera type for the resolution")
     ap.add_argument("--pool", type=int, default=3000)
     ap.add_argument("--stream", type=int, default=1_000_000)
+    ap.add_argument("--only", default="", help="comma-separated extractor names for the throughput "
+                    "(%s; default all); with --events 0 the resolution is skipped" % ",".join(NAMES.values()))
     args = ap.parse_args()
+    only = [n for n in args.only.split(",") if n]
+    for n in only:
+        if n not in NAMES.values():
+            ap.error("unknown extractor %r" % n)
     dev = torch.device("cuda:0")
     say = lambda s: print(s, flush=True)  # noqa: E731
     t0 = time.time()
-    res = {"resolution": resolution(dl0sim.camera_types_c1(), args.events, dev, log=say)}
-    res["throughput"] = throughput(args.pool, args.stream, dev, log=say)
+    res = {"resolution": resolution(dl0sim.camera_types_c1(), args.events, dev, log=say) if args.events > 0 else {}}
+    res["throughput"] = throughput(args.pool, args.stream, dev, log=say, only=only)
     res["seconds"] = time.time() - t0
     print(json.dumps(res), flush=True)
 
