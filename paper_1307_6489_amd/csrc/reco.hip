@@ -651,12 +651,11 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
   auto slot = [](uint32_t j) { return (j & ~7u) | ((j ^ (j >> 3)) & 7u); };
   uint32_t nb[MAXK][3];  // six neighbour words per position: LDS byte offsets, 16 bits each (word Npad if missing)
   uint32_t ring[MAXK][W - 1];
-  uint32_t best[MAXK], hmax[MAXK], hmax2[MAXK], pix[MAXK];
+  uint32_t best[MAXK], hmax2[MAXK];
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) {
     const int p = (int)threadIdx.x + k * NT;
     nb[k][0] = nb[k][1] = nb[k][2] = (uint32_t)np * 8u * 0x10001u;
-    pix[k] = 0;
     if (p < N) {
       const int4 v = *reinterpret_cast<const int4*>(c.lat + (size_t)p * kNbrCols);
       const uint32_t w3[3] = {(uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z};
@@ -666,12 +665,10 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
         const uint32_t hi = (w3[h] & 0x80000000u) ? (uint32_t)np : slot(w3[h] >> 16);
         nb[k][h] = (lo << 3) | (hi << 19);  // (Npad + 1) * 8 bytes < 2^16
       }
-      pix[k] = (uint32_t)v.w & 0xffffu;
     }
 #pragma unroll
     for (int u = 0; u < W - 1; ++u) ring[k][u] = 0;
     best[k] = 0;
-    hmax[k] = 0;
     hmax2[k] = 0;
   }
   if (threadIdx.x == 0) xs[np] = 0ull;
@@ -697,6 +694,12 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
   };
   if (stager) load4(0);
   for (int k0 = 0; k0 < T; k0 += kNbrRows) {
+    // keep the neighbour offsets packed: unpacked out of the loop they
+    // would take six registers per position instead of three
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k)
+#pragma unroll
+      for (int h = 0; h < 3; ++h) asm volatile("" : "+v"(nb[k][h]));
     __syncthreads();  // the previous slices are consumed
     if (stager) {
 #pragma unroll
@@ -772,7 +775,7 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
       for (int u = 0; u < kNbrRows; ++u) {
         const int t = k0 + u;
         if (t >= T) break;
-        hmax[k] = max(hmax[k], xo[u]);
+        hmax2[k] = max(hmax2[k] & 0xffffu, xo[u]) | (hmax2[k] & 0xffff0000u);
         uint32_t C = y[u];
 #pragma unroll
         for (int z = 0; z < W - 1; ++z) C += ring[k][z];
@@ -788,8 +791,11 @@ __device__ __forceinline__ void neighbour_event(const DevCam& c, __amdgpu_buffer
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) {
     const int p = (int)threadIdx.x + k * NT;
-    const uint32_t hm = max(hmax[k], max(lo16(hmax2[k]), hi16(hmax2[k])));
-    if (p < N) keys[pix[k]] = best[k] | ((dual && (int)hm >= c.hg_switch) ? 0x80000000u : 0u);
+    const uint32_t hm = max(lo16(hmax2[k]), hi16(hmax2[k]));
+    if (p < N) {
+      const uint32_t pix = (uint32_t)c.lat[(size_t)p * kNbrCols + 6] & 0xffffu;  // the pixel at position p
+      keys[pix] = best[k] | ((dual && (int)hm >= c.hg_switch) ? 0x80000000u : 0u);
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -1268,6 +1274,14 @@ __device__ __forceinline__ void bad_record(rta_hillas_rec* out) {
   *out = r;
 }
 
+// Waves per SIMD the register allocation must leave room for: the neighbour
+// peak's 256-thread workgroups fit four to a compute unit by their LDS, if
+// the registers allow it.  Elsewhere the compiler's own choice stands.
+template <int EX, int NT>
+constexpr int min_waves() {
+  return EX == kExNeighbour && NT == 256 ? 4 : 1;
+}
+
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
@@ -1473,7 +1487,8 @@ __global__ __launch_bounds__(NT) void k_fused(FusedArgs a) {
 // workgroup scheduler (no loop-carried state, so no register pressure from
 // values hoisted across telescopes).
 template <int EX, int PPL, int W, int CH, int NT>
-__global__ __launch_bounds__(NT) void k_fused_grid(FusedArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(min_waves<EX, NT>()))) void k_fused_grid(
+    FusedArgs a) {
   __shared__ TelSmem sm;
   fused_telescope<EX, PPL, W, CH, NT>(a, (long long)blockIdx.x, sm);
 }
