@@ -5,12 +5,15 @@
 // separation and energy steps that the paper lists among the reconstruction
 // products (Section 4.1).  Operands are bfloat16, accumulation FP32.
 //
-// Register layout.  Every layer is computed transposed, Z^T = W^T . H^T, with
-// v_mfma_f32_16x16x16_bf16 on 16x16 tiles: A = a 16x16 block of W^T (rows =
-// output features), B = a 16-feature x 16-row block of H^T, C/D = 16 output
-// features x 16 rows.  In that orientation the accumulator layout (lane l:
-// row-of-batch l%16, features 4*(l/16)..+3) is exactly the B-operand layout of
-// the next layer, so activations go from one layer to the next in registers.
+// Register layout.  Every layer is computed transposed, Z^T = W^T . H^T, on
+// 16x16 tiles: A = a block of W^T (rows = output features), B = a block of
+// H^T (features x 16 rows), C/D = 16 output features x 16 rows.  In that
+// orientation the accumulator layout (lane l: row-of-batch l%16, features
+// 4*(l/16)..+3) is exactly the B-operand layout of a 16-feature block, so
+// activations go from one layer to the next in registers.  Contractions over
+// 64 features (or over the batch) take two 16-blocks per
+// v_mfma_f32_16x16x32_bf16, the two blocks' B fragments side by side; the
+// 16-wide input and output layers use v_mfma_f32_16x16x16_bf16.
 // The backward pass uses the same trick with the untransposed weights.  Weight
 // gradients contract over the batch, so per-row activations and gradients are
 // written feature-major ([F][B], bf16) and wavefronts, one per 16x16 weight
@@ -106,7 +109,9 @@ __global__ __launch_bounds__(kRowsNT) void k_mlp_rows(MlpDev w, const float* __r
   for (int t = 0; t < 4; ++t) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = mfma(load4(w.W3n, kHid, 16 * t + col, 16 * u + 4 * grp), g3[u], acc);
+    for (int u = 0; u < 4; u += 2)
+      acc = mfma2(load4(w.W3n, kHid, 16 * t + col, 16 * u + 4 * grp),
+                  load4(w.W3n, kHid, 16 * t + col, 16 * (u + 1) + 4 * grp), g3[u], g3[u + 1], acc);
     g2[t] = mask_bf(acc, h2[t]);
     store4T(w.G2, Bpad, 16 * t + 4 * grp, b, g2[t]);
   }
@@ -114,7 +119,9 @@ __global__ __launch_bounds__(kRowsNT) void k_mlp_rows(MlpDev w, const float* __r
   for (int t = 0; t < 4; ++t) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = mfma(load4(w.W2n, kHid, 16 * t + col, 16 * u + 4 * grp), g2[u], acc);
+    for (int u = 0; u < 4; u += 2)
+      acc = mfma2(load4(w.W2n, kHid, 16 * t + col, 16 * u + 4 * grp),
+                  load4(w.W2n, kHid, 16 * t + col, 16 * (u + 1) + 4 * grp), g2[u], g2[u + 1], acc);
     g1v[t] = mask_bf(acc, h1[t]);
     store4T(w.G1, Bpad, 16 * t + 4 * grp, b, g1v[t]);
   }
@@ -175,9 +182,13 @@ __global__ __launch_bounds__(64) void k_mlp_grad(MlpDev w, int B, int Bpad, floa
         b[u] = load4(G, Bpad, out0 + col, 16 * (k + u) + 4 * grp);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc = mfma(a[u], b[u], acc);
+      for (int u = 0; u < 4; u += 2) acc = mfma2(a[u], a[u + 1], b[u], b[u + 1], acc);
     }
-    for (; k < k1; ++k)
+    for (; k + 2 <= k1; k += 2)
+      acc = mfma2(load4(H, Bpad, in0 + col, 16 * k + 4 * grp), load4(H, Bpad, in0 + col, 16 * (k + 1) + 4 * grp),
+                  load4(G, Bpad, out0 + col, 16 * k + 4 * grp), load4(G, Bpad, out0 + col, 16 * (k + 1) + 4 * grp),
+                  acc);
+    if (k < k1)
       acc = mfma(load4(H, Bpad, in0 + col, 16 * k + 4 * grp), load4(G, Bpad, out0 + col, 16 * k + 4 * grp), acc);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -199,9 +210,12 @@ __global__ __launch_bounds__(64) void k_mlp_grad(MlpDev w, int B, int Bpad, floa
 #pragma unroll
         for (int u = 0; u < 4; ++u) b[u] = load4(G, Bpad, 16 * c + col, 16 * (k + u) + 4 * grp);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc = mfma(ones, b[u], acc);
+        for (int u = 0; u < 4; u += 2) acc = mfma2(ones, ones, b[u], b[u + 1], acc);
       }
-      for (; k < k1; ++k) acc = mfma(ones, load4(G, Bpad, 16 * c + col, 16 * k + 4 * grp), acc);
+      for (; k + 2 <= k1; k += 2)
+        acc = mfma2(ones, ones, load4(G, Bpad, 16 * c + col, 16 * k + 4 * grp),
+                    load4(G, Bpad, 16 * c + col, 16 * (k + 1) + 4 * grp), acc);
+      if (k < k1) acc = mfma(ones, load4(G, Bpad, 16 * c + col, 16 * k + 4 * grp), acc);
       const int n = 16 * c + col;
       if (grp == 0 && n < dim) part[off + n] = acc[0];
     }

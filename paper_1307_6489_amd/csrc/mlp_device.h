@@ -30,8 +30,22 @@ __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
   return v;
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// One 16x16 tile product over K = 16 (v_mfma_f32_16x16x16_bf16).
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// One 16x16 tile product over two K = 16 blocks at once
+// (v_mfma_f32_16x16x32_bf16): lane group g supplies eight k slots, the
+// four of block 0 then the four of block 1 that the K = 16 layout gives it.
+// Both operands use the same slot order, so the contraction is the sum over
+// both blocks whatever k each slot stands for.
+__device__ __forceinline__ f32x4 mfma2(bf16x4 a0, bf16x4 a1, bf16x4 b0, bf16x4 b1, f32x4 c) {
+  const bf16x8 a = __builtin_bit_cast(bf16x8, __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7));
+  const bf16x8 b = __builtin_bit_cast(bf16x8, __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7));
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 // A operand: 4 consecutive bf16 of row `row` starting at column `col0`.
@@ -78,19 +92,25 @@ __device__ __forceinline__ f32x4 mlp_forward_tile(const MlpDev& w, bf16x4 xin, b
   for (int t = 0; t < 4; ++t) {
     f32x4 acc = bias4(w.b2, 16 * t + 4 * grp);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = mfma(load4(w.W2t, kHid, 16 * t + col, 16 * u + 4 * grp), h1[u], acc);
+    for (int u = 0; u < 4; u += 2)
+      acc = mfma2(load4(w.W2t, kHid, 16 * t + col, 16 * u + 4 * grp),
+                  load4(w.W2t, kHid, 16 * t + col, 16 * (u + 1) + 4 * grp), h1[u], h1[u + 1], acc);
     h2[t] = relu_bf(acc);
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     f32x4 acc = bias4(w.b3, 16 * t + 4 * grp);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = mfma(load4(w.W3t, kHid, 16 * t + col, 16 * u + 4 * grp), h2[u], acc);
+    for (int u = 0; u < 4; u += 2)
+      acc = mfma2(load4(w.W3t, kHid, 16 * t + col, 16 * u + 4 * grp),
+                  load4(w.W3t, kHid, 16 * t + col, 16 * (u + 1) + 4 * grp), h2[u], h2[u + 1], acc);
     h3[t] = relu_bf(acc);
   }
   f32x4 out = bias4(w.b4, 4 * grp);
 #pragma unroll
-  for (int u = 0; u < 4; ++u) out = mfma(load4(w.W4t, kHid, col, 16 * u + 4 * grp), h3[u], out);
+  for (int u = 0; u < 4; u += 2)
+    out = mfma2(load4(w.W4t, kHid, col, 16 * u + 4 * grp), load4(w.W4t, kHid, col, 16 * (u + 1) + 4 * grp), h3[u],
+                h3[u + 1], out);
   return out;
 }
 
