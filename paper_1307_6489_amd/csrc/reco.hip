@@ -932,6 +932,7 @@ struct TelSmem {
     uint16_t xrow[kNbrRows * (kMaxPix + 8)];  // neighbour peak: staged slices + zero slot (extraction only)
   };
   double red[16 * 8];        // cross-wave reduction scratch
+  int32_t nlow_w[16];        // per-wave counts of low-gain pixels
   int32_t start;             // global peak window start
 };
 
@@ -982,6 +983,35 @@ __device__ __forceinline__ void block_sum(T (&v)[NV], double* red_raw) {
     v[k] = s;
   }
   __syncthreads();
+}
+
+// The same sums over one wavefront (the other wavefronts hold nothing): the
+// butterfly of block_sum, then its cross-wave sum, here 0 + the wave's sum.
+template <typename T, int NV>
+__device__ __forceinline__ void wave_sum(T (&v)[NV]) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, kWave);
+    v[k] = T(0) + v[k];
+  }
+}
+
+// Workgroup total of a per-thread count: each wavefront's sum goes to
+// sm.nlow_w before a barrier the caller provides; total_count reads them
+// after it.
+__device__ __forceinline__ void post_count(TelSmem& sm, int v) {
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) sm.nlow_w[threadIdx.x / kWave] = v;
+}
+
+template <int NT>
+__device__ __forceinline__ int total_count(const TelSmem& sm) {
+  int s = 0;
+#pragma unroll
+  for (int w = 0; w < NT / kWave; ++w) s += sm.nlow_w[w];
+  return s;
 }
 
 __device__ __forceinline__ bool mask_bit(const TelSmem& sm, int i) { return (sm.mbits[i >> 6] >> (i & 63)) & 1ull; }
@@ -1124,13 +1154,18 @@ __device__ __forceinline__ void uf_union(int32_t* par, int a, int b) {
 
 // Phase 5: islands = roots of the union-find forest over mask slots.
 // Returns this thread's root count.  The per-pixel keys (no longer needed)
-// hold the parents.
-template <int NT>
+// hold the parents.  WAVE: wavefront 0 alone, over at most 64 slots, the
+// barriers replaced by wavefront-scope ordering of its LDS accesses.
+template <int NT, bool WAVE>
 __device__ __forceinline__ int islands_phase(const DevCam& c, TelSmem& sm, int n) {
+  constexpr int STEP = WAVE ? kWave : NT;
   int32_t* par = reinterpret_cast<int32_t*>(sm.key);
-  for (int j = threadIdx.x; j < n; j += NT) par[j] = j;
-  __syncthreads();
-  for (int j = threadIdx.x; j < n; j += NT) {
+  for (int j = threadIdx.x; j < n; j += STEP) par[j] = j;
+  if constexpr (WAVE)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  else
+    __syncthreads();
+  for (int j = threadIdx.x; j < n; j += STEP) {
     const int i = sm.list[j] & 0x7FFF;
     const int4 nv = *reinterpret_cast<const int4*>(c.nbr + (size_t)i * kNbrCols);
     const int16_t* nb = reinterpret_cast<const int16_t*>(&nv);
@@ -1140,9 +1175,12 @@ __device__ __forceinline__ int islands_phase(const DevCam& c, TelSmem& sm, int n
       if (m > i && mask_bit(sm, m)) uf_union(par, j, mask_slot(sm, m));
     }
   }
-  __syncthreads();
+  if constexpr (WAVE)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  else
+    __syncthreads();
   int roots = 0;
-  for (int j = threadIdx.x; j < n; j += NT) roots += (((volatile int32_t*)par)[j] == j);
+  for (int j = threadIdx.x; j < n; j += STEP) roots += (((volatile int32_t*)par)[j] == j);
   return roots;
 }
 
@@ -1156,10 +1194,11 @@ __device__ __forceinline__ int islands_phase(const DevCam& c, TelSmem& sm, int n
 // absolute sample numbers, so FP32 would cancel most digits of small time
 // gradients; in FP64 the centring cancels about t / spread(t) x mean(l) /
 // spread(l) digits, harmless).
-template <int NT, int W, bool FUSED>
+template <int NT, int W, bool FUSED, bool WAVE>
 __device__ __forceinline__ rta_hillas_rec hillas_phase(const DevCam& c, TelSmem& sm, int n, int roots, int nlow) {
-  float v1[6] = {0.f, 0.f, 0.f, 0.f, (float)roots, (float)nlow};
-  for (int j = threadIdx.x; j < n; j += NT) {
+  constexpr int STEP = WAVE ? kWave : NT;
+  float v1[5] = {0.f, 0.f, 0.f, 0.f, (float)roots};
+  for (int j = threadIdx.x; j < n; j += STEP) {
     const int i = sm.list[j] & 0x7FFF;
     const float q = slot_q<FUSED>(c, sm, j, i);
     v1[0] += q;
@@ -1167,13 +1206,16 @@ __device__ __forceinline__ rta_hillas_rec hillas_phase(const DevCam& c, TelSmem&
     v1[2] += q * c.y[i];
     if (c.border[i]) v1[3] += q;
   }
-  block_sum<float, 6, NT>(v1, sm.red);
+  if constexpr (WAVE)
+    wave_sum(v1);
+  else
+    block_sum<float, 5, NT>(v1, sm.red);
   const float S = v1[0];
   rta_hillas_rec r;
   r.size = S;
   r.n_pix = n;
   r.n_islands = (int32_t)v1[4];
-  r.n_lowgain = (int32_t)v1[5];
+  r.n_lowgain = nlow;
   r.flags = r.n_lowgain > 0 ? RTA_FLAG_LOW_GAIN : 0u;
   if (n < 2 || !(S > 0.f)) {
     r.cog_x = r.cog_y = r.length = r.width = r.psi = r.skewness = r.kurtosis = kNaN;
@@ -1183,14 +1225,17 @@ __device__ __forceinline__ rta_hillas_rec hillas_phase(const DevCam& c, TelSmem&
   }
   const float xm = v1[1] / S, ym = v1[2] / S;
   float v2[3] = {0.f, 0.f, 0.f};
-  for (int j = threadIdx.x; j < n; j += NT) {
+  for (int j = threadIdx.x; j < n; j += STEP) {
     const int i = sm.list[j] & 0x7FFF;
     const float q = slot_q<FUSED>(c, sm, j, i), dx = c.x[i] - xm, dy = c.y[i] - ym;
     v2[0] += q * dx * dx;
     v2[1] += q * dy * dy;
     v2[2] += q * dx * dy;
   }
-  block_sum<float, 3, NT>(v2, sm.red);
+  if constexpr (WAVE)
+    wave_sum(v2);
+  else
+    block_sum<float, 3, NT>(v2, sm.red);
   const float sxx = v2[0] / S, syy = v2[1] / S, sxy = v2[2] / S;
   const float hd = 0.5f * (sxx - syy);
   const float lp = 0.5f * (sxx + syy) + sqrtf(hd * hd + sxy * sxy);
@@ -1207,7 +1252,7 @@ __device__ __forceinline__ rta_hillas_rec hillas_phase(const DevCam& c, TelSmem&
   }
   // q l^3, q l^4, q w^2, l, l^2, t, l t, |l - l0|
   double v3[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int j = threadIdx.x; j < n; j += NT) {
+  for (int j = threadIdx.x; j < n; j += STEP) {
     const int i = sm.list[j] & 0x7FFF;
     const float q = slot_q<FUSED>(c, sm, j, i), dx = c.x[i] - xm, dy = c.y[i] - ym;
     const float l = dx * cs + dy * sn;
@@ -1223,7 +1268,10 @@ __device__ __forceinline__ rta_hillas_rec hillas_phase(const DevCam& c, TelSmem&
     v3[6] += ld * td;
     v3[7] += fabs(ld - (double)l0);
   }
-  block_sum<double, 8, NT>(v3, sm.red);
+  if constexpr (WAVE)
+    wave_sum(v3);
+  else
+    block_sum<double, 8, NT>(v3, sm.red);
   const double nd = (double)n, lbar = v3[3] / nd, tbar = v3[5] / nd;
   const double sll = v3[4] - v3[3] * lbar, slt = v3[6] - v3[3] * tbar;
   r.cog_x = xm;
@@ -1247,12 +1295,29 @@ __device__ __forceinline__ rta_hillas_rec hillas_phase(const DevCam& c, TelSmem&
   return r;
 }
 
-// Calibration -> cleaning -> Hillas of one camera event; every thread
-// returns the same record.
+// Phases 5 and 6 over the n mask slots; nlow: the image's low-gain pixel
+// count.  An image of at most 64 mask pixels (most images) is done by
+// wavefront 0 alone, with no barrier, while the other wavefronts return an
+// unused record at once; the sums are the same bit for bit, since the other
+// wavefronts would contribute exact zeros.  The threads of wavefront 0
+// return the record.
+template <int NT, int W, bool FUSED>
+__device__ __forceinline__ rta_hillas_rec islands_hillas(const DevCam& c, TelSmem& sm, int n, int nlow) {
+  if (n <= kWave) {
+    if (threadIdx.x >= kWave) return rta_hillas_rec{};
+    const int roots = islands_phase<NT, true>(c, sm, n);
+    return hillas_phase<NT, W, FUSED, true>(c, sm, n, roots, nlow);
+  }
+  const int roots = islands_phase<NT, false>(c, sm, n);
+  return hillas_phase<NT, W, FUSED, false>(c, sm, n, roots, nlow);
+}
+
+// Calibration -> cleaning -> Hillas of one camera event; the threads of
+// wavefront 0 return the record.
 template <int EX, int PPL, int W, int CH, int NT>
 __device__ __forceinline__ rta_hillas_rec process_telescope(const DevCam& c, const uint16_t* __restrict__ ev,
                                                             TelSmem& sm) {
-  const int nlow = extract_phase<EX, PPL, W, CH, NT>(c, ev, sm);
+  post_count(sm, extract_phase<EX, PPL, W, CH, NT>(c, ev, sm));
   __syncthreads();
   mask_phase<NT>(c, sm);
   __syncthreads();
@@ -1261,8 +1326,7 @@ __device__ __forceinline__ rta_hillas_rec process_telescope(const DevCam& c, con
   const int n = sm.wbase[(c.n_pix + 63) >> 6];
   list_phase<NT, W, true>(c, sm, ev, nullptr, nullptr, nullptr);
   __syncthreads();
-  const int roots = islands_phase<NT>(c, sm, n);
-  return hillas_phase<NT, W, true>(c, sm, n, roots, nlow);
+  return islands_hillas<NT, W, true>(c, sm, n, total_count<NT>(sm));
 }
 
 __device__ __forceinline__ void bad_record(rta_hillas_rec* out) {
@@ -1385,14 +1449,14 @@ __global__ __launch_bounds__(NT) void k_hillas(DevCam c, const int32_t* __restri
     const uint64_t b = __ballot(m);
     if (lane == 0) sm.mbits[base >> 6] = b;
   }
+  post_count(sm, nlow);
   __syncthreads();
   scan_phase(N, sm);
   __syncthreads();
   const int n = sm.wbase[nw];
   list_phase<NT, W, false>(c, sm, nullptr, D + ob, gain ? gain + ob : nullptr, t + ob);
   __syncthreads();
-  const int roots = islands_phase<NT>(c, sm, n);
-  const rta_hillas_rec r = hillas_phase<NT, W, false>(c, sm, n, roots, nlow);
+  const rta_hillas_rec r = islands_hillas<NT, W, false>(c, sm, n, total_count<NT>(sm));
   if (threadIdx.x == 0) out[e] = r;
 }
 
