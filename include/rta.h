@@ -249,16 +249,39 @@ rta_status rta_calibrate_ex(const rta_camera* cam, int32_t extractor, const uint
                             int32_t* S, int32_t* D, uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q,
                             float* t, rta_stream stream);
 
-/* Two-level tailcut of n_evt events.  D, gain: [n_evt][N] (gain NULLABLE =
- * all high gain).  mask: [n_evt][N] 0/1. */
-rta_status rta_clean(const rta_camera* cam, const int32_t* D, const uint8_t* gain, int64_t n_evt, uint8_t* mask,
-                     rta_stream stream);
+/* Cleaning levels of one rta_clean call, photo-electrons. */
+typedef struct rta_clean_params {
+  float t_pic;              /* picture level */
+  float t_bnd;              /* boundary level, <= t_pic */
+} rta_clean_params;
 
-/* Hillas parameters of n_evt events from calibrated charges (D in Q8 units
- * and its gain, NULLABLE = all high gain), times t and the mask, all
- * [n_evt][N].  out: [n_evt] records. */
-rta_status rta_hillas(const rta_camera* cam, const int32_t* D, const uint8_t* gain, const float* t,
-                      const uint8_t* mask, int64_t n_evt, rta_hillas_rec* out, rta_stream stream);
+/* Two-level tailcut (image cleaning, Section 4.1) of n_evt events: a pixel
+ * stays if it is at or above the boundary level with a neighbour at or above
+ * the picture level, or at or above the picture level with a neighbour at or
+ * above the boundary level, on the integer thresholds ceil(256 a T) of D
+ * (Q8).  levels: NULLABLE host struct; NULL takes the camera's levels (the
+ * ones the fused path uses); otherwise finite with t_bnd <= t_pic and
+ * |256 a T| <= 2e9 for every pixel's a, else RTA_E_INVALID_ARG.  D, gain:
+ * [n_evt][N] device (gain NULLABLE = all high gain).  mask: [n_evt][N] 0/1. */
+rta_status rta_clean(const rta_camera* cam, const rta_clean_params* levels, const int32_t* D, const uint8_t* gain,
+                     int64_t n_evt, uint8_t* mask, rta_stream stream);
+
+/* Hillas parameters (Section 4.1) of n_evt events from calibrated charges
+ * q_pe (p.e., as rta_calibrate writes them), peak times t (samples) and the
+ * cleaning mask, all [n_evt][N] device.  gain: NULLABLE [n_evt][N]; when
+ * given, the record's n_lowgain and RTA_FLAG_LOW_GAIN count the low-gain
+ * pixels of the image (as the fused path does); NULL counts none.  out:
+ * [n_evt] records.  With q_pe and t from rta_calibrate and the mask from
+ * rta_clean, every field but the time regression equals the fused path's
+ * record bit for bit (the fused path keeps peak times in FP64, t is FP32). */
+rta_status rta_hillas(const rta_camera* cam, const float* q_pe, const float* t, const uint8_t* mask,
+                      const uint8_t* gain, int64_t n_evt, rta_hillas_rec* out, rta_stream stream);
+/* The same from the integer calibration output: D (Q8, [n_evt][N] device)
+ * and its gain (NULLABLE = all high gain, then also no low-gain count); the
+ * charge D / (256 a) is formed in the kernel as rta_calibrate forms q_pe, so
+ * the records equal rta_hillas's on rta_calibrate's q_pe and gain. */
+rta_status rta_hillas_q8(const rta_camera* cam, const int32_t* D, const float* t, const uint8_t* mask,
+                         const uint8_t* gain, int64_t n_evt, rta_hillas_rec* out, rta_stream stream);
 
 /* A pipeline over 1..RTA_MAX_TYPES camera types (the handles must outlive it). */
 rta_status rta_pipeline_create(rta_camera* const* cams, int32_t n_types, const rta_pipeline_params* params,

@@ -129,8 +129,9 @@ SYMBOLS = {
     "rta_camera_get_info": ([_vp, _vp], ctypes.c_int),
     "rta_calibrate": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "rta_calibrate_ex": ([_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
-    "rta_clean": ([_vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
+    "rta_clean": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_hillas": ([_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
+    "rta_hillas_q8": ([_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp], ctypes.c_int),
     "rta_pipeline_create": ([_vp, _i32, _vp, _vp], ctypes.c_int),
     "rta_pipeline_destroy": ([_vp], ctypes.c_int),
     "rta_set_schedule": ([_vp, _vp], ctypes.c_int),
@@ -356,19 +357,42 @@ def calibrate(cam: Camera, traces, stream=None, outputs=("S", "D", "sstar", "pea
     return out
 
 
-def clean(cam: Camera, D, gain=None, stream=None):
+class CleanParams(ctypes.Structure):
+    _fields_ = [("t_pic", ctypes.c_float), ("t_bnd", ctypes.c_float)]
+
+
+def clean(cam: Camera, D, gain=None, stream=None, levels=None):
+    """rta_clean; levels: optional (t_pic, t_bnd) in p.e. (default: the
+    camera's levels)."""
     import torch
     _require(D, torch.int32, name="D")
     E = D.numel() // cam.n_pix
     _require(D, torch.int32, (E, cam.n_pix), "D")
     if gain is not None:
         _require(gain, torch.uint8, (E, cam.n_pix), "gain")
+    lv = None if levels is None else ctypes.byref(CleanParams(float(levels[0]), float(levels[1])))
     mask = torch.empty((E, cam.n_pix), dtype=torch.uint8, device=D.device)
-    _check(lib().rta_clean(cam.handle, _ptr(D), _ptr(gain), E, _ptr(mask), _stream(stream)))
+    _check(lib().rta_clean(cam.handle, lv, _ptr(D), _ptr(gain), E, _ptr(mask), _stream(stream)))
     return mask
 
 
-def hillas(cam: Camera, D, gain, t, mask, stream=None):
+def hillas(cam: Camera, q, t, mask, gain=None, stream=None):
+    """rta_hillas: records from charges q (p.e.), times t and the mask; gain
+    (optional) for the low-gain pixel count."""
+    import torch
+    E = q.numel() // cam.n_pix
+    _require(q, torch.float32, (E, cam.n_pix), "q")
+    _require(t, torch.float32, (E, cam.n_pix), "t")
+    _require(mask, torch.uint8, (E, cam.n_pix), "mask")
+    if gain is not None:
+        _require(gain, torch.uint8, (E, cam.n_pix), "gain")
+    out = torch.empty((E, 16), dtype=torch.float32, device=q.device)
+    _check(lib().rta_hillas(cam.handle, _ptr(q), _ptr(t), _ptr(mask), _ptr(gain), E, _ptr(out), _stream(stream)))
+    return out
+
+
+def hillas_q8(cam: Camera, D, t, mask, gain=None, stream=None):
+    """rta_hillas_q8: records from the integer charges D (Q8) and their gain."""
     import torch
     E = D.numel() // cam.n_pix
     _require(D, torch.int32, (E, cam.n_pix), "D")
@@ -377,7 +401,7 @@ def hillas(cam: Camera, D, gain, t, mask, stream=None):
     if gain is not None:
         _require(gain, torch.uint8, (E, cam.n_pix), "gain")
     out = torch.empty((E, 16), dtype=torch.float32, device=D.device)
-    _check(lib().rta_hillas(cam.handle, _ptr(D), _ptr(gain), _ptr(t), _ptr(mask), E, _ptr(out), _stream(stream)))
+    _check(lib().rta_hillas_q8(cam.handle, _ptr(D), _ptr(t), _ptr(mask), _ptr(gain), E, _ptr(out), _stream(stream)))
     return out
 
 

@@ -909,6 +909,17 @@ __device__ __forceinline__ uint32_t pixel_flag(const DevCam& c, int g, int i, in
   return (uint32_t)(d >= c.thr_bnd[o]) | ((uint32_t)(d >= c.thr_pic[o]) << 1);
 }
 
+// The same with given levels (p.e.): the thresholds ceil(256 a T) formed in
+// FP64 in the order the camera creation forms its tables (256 a is exact,
+// then one rounded product), so the levels the camera was made with give
+// its tables' values.  The host bounds them to |.| <= 2e9.
+__device__ __forceinline__ uint32_t pixel_flag_at(const DevCam& c, int g, int i, int32_t d, float t_pic,
+                                                  float t_bnd) {
+  const double a256 = 256.0 * (double)c.a[g * c.n_pix_pad + i];
+  const int32_t tp = (int32_t)ceil(a256 * (double)t_pic), tb = (int32_t)ceil(a256 * (double)t_bnd);
+  return (uint32_t)(d >= tb) | ((uint32_t)(d >= tp) << 1);
+}
+
 // ---------------------------------------------------------------------------
 // Workgroup-shared state of one camera event.
 // ---------------------------------------------------------------------------
@@ -939,12 +950,16 @@ struct TelSmem {
 __device__ __forceinline__ int32_t sext28(uint32_t v) { return (int32_t)(v << 4) >> 4; }
 
 // Charge of slot j: q = D / (256 a), formed where it is used (the same float
-// every time).
+// every time, and the float the calibration writes as q); on the unfused
+// path the given q.
 template <bool FUSED>
 __device__ __forceinline__ float slot_q(const DevCam& c, const TelSmem& sm, int j, int i) {
-  const int g = sm.list[j] >> 15;
-  const int32_t D = FUSED ? sext28(sm.slot.dq[j]) : (int32_t)sm.slot.dq[j];
-  return (float)D / (256.0f * c.a[g * c.n_pix_pad + i]);
+  if constexpr (FUSED) {
+    const int g = sm.list[j] >> 15;
+    return (float)sext28(sm.slot.dq[j]) / (256.0f * c.a[g * c.n_pix_pad + i]);
+  } else {
+    return __uint_as_float(sm.slot.dq[j]);
+  }
 }
 
 // Peak time of slot j (samples): s* + Nt / D from the packed slot, or the
@@ -1101,8 +1116,8 @@ __device__ __forceinline__ void scan_phase(int N, TelSmem& sm) {
 // gain and t come from global arrays of this event.
 template <int NT, int W, bool FUSED>
 __device__ __forceinline__ void list_phase(const DevCam& c, TelSmem& sm, const uint16_t* __restrict__ ev,
-                                           const int32_t* __restrict__ Dg, const uint8_t* __restrict__ gg,
-                                           const float* __restrict__ tg) {
+                                           const float* __restrict__ qg, const int32_t* __restrict__ Dg,
+                                           const uint8_t* __restrict__ gg, const float* __restrict__ tg) {
   const int N = c.n_pix, nw = (N + 63) >> 6, np = c.n_pix_pad;
   const int lane = threadIdx.x & (kWave - 1);
   for (int base = threadIdx.x & ~(kWave - 1); base < nw * kWave; base += NT) {
@@ -1121,9 +1136,11 @@ __device__ __forceinline__ void list_phase(const DevCam& c, TelSmem& sm, const u
         sm.slot.dq[j] = ((uint32_t)d & 0x0FFFFFFFu) | ((uint32_t)(s >> 4) << 28);
         sm.slot.nt[j] = ((uint32_t)nt & 0x0FFFFFFFu) | ((uint32_t)(s & 15) << 28);
       } else {
+        // the given charge, or D / (256 a) formed as the calibration forms q
         const int g = gg ? (int)gg[i] : 0;
+        const float q = qg ? qg[i] : (float)Dg[i] / (256.0f * c.a[g * np + i]);
         sm.list[j] = (uint16_t)(i | (g << 15));
-        sm.slot.dq[j] = (uint32_t)Dg[i];
+        sm.slot.dq[j] = __float_as_uint(q);
         sm.slot.nt[j] = __float_as_uint(tg[i]);
       }
     }
@@ -1324,7 +1341,7 @@ __device__ __forceinline__ rta_hillas_rec process_telescope(const DevCam& c, con
   scan_phase(c.n_pix, sm);
   __syncthreads();
   const int n = sm.wbase[(c.n_pix + 63) >> 6];
-  list_phase<NT, W, true>(c, sm, ev, nullptr, nullptr, nullptr);
+  list_phase<NT, W, true>(c, sm, ev, nullptr, nullptr, nullptr, nullptr);
   __syncthreads();
   return islands_hillas<NT, W, true>(c, sm, n, total_count<NT>(sm));
 }
@@ -1417,14 +1434,15 @@ __global__ __launch_bounds__(NT) void k_calibrate(DevCam c, const uint16_t* __re
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_clean(DevCam c, const int32_t* __restrict__ D, const uint8_t* __restrict__ gain,
-                                              uint8_t* __restrict__ mask) {
+                                              uint8_t* __restrict__ mask, int have_levels, float t_pic, float t_bnd) {
   __shared__ TelSmem sm;
   const int64_t e = blockIdx.x;
   const int N = c.n_pix;
   const size_t ob = (size_t)e * N;
   for (int i = threadIdx.x; i < N; i += NT) {
     const int g = gain ? (int)gain[ob + i] : 0;
-    sm.flag[i] = (uint8_t)pixel_flag(c, g, i, D[ob + i]);
+    sm.flag[i] = (uint8_t)(have_levels ? pixel_flag_at(c, g, i, D[ob + i], t_pic, t_bnd)
+                                       : pixel_flag(c, g, i, D[ob + i]));
   }
   __syncthreads();
   mask_phase<NT>(c, sm);
@@ -1433,9 +1451,9 @@ __global__ __launch_bounds__(NT) void k_clean(DevCam c, const int32_t* __restric
 }
 
 template <int W, int NT>
-__global__ __launch_bounds__(NT) void k_hillas(DevCam c, const int32_t* __restrict__ D,
-                                               const uint8_t* __restrict__ gain, const float* __restrict__ t,
-                                               const uint8_t* __restrict__ mask, rta_hillas_rec* out) {
+__global__ __launch_bounds__(NT) void k_hillas(DevCam c, const float* __restrict__ q, const int32_t* __restrict__ D,
+                                               const float* __restrict__ t, const uint8_t* __restrict__ mask,
+                                               const uint8_t* __restrict__ gain, rta_hillas_rec* out) {
   __shared__ TelSmem sm;
   const int64_t e = blockIdx.x;
   const int N = c.n_pix, nw = (N + 63) >> 6;
@@ -1454,7 +1472,8 @@ __global__ __launch_bounds__(NT) void k_hillas(DevCam c, const int32_t* __restri
   scan_phase(N, sm);
   __syncthreads();
   const int n = sm.wbase[nw];
-  list_phase<NT, W, false>(c, sm, nullptr, D + ob, gain ? gain + ob : nullptr, t + ob);
+  list_phase<NT, W, false>(c, sm, nullptr, q ? q + ob : nullptr, D ? D + ob : nullptr, gain ? gain + ob : nullptr,
+                           t + ob);
   __syncthreads();
   const rta_hillas_rec r = islands_hillas<NT, W, false>(c, sm, n, total_count<NT>(sm));
   if (threadIdx.x == 0) out[e] = r;
@@ -1747,9 +1766,9 @@ hipError_t launch_calibrate_w(const DevCam& c, int ex, const uint16_t* tr, int64
 }
 
 template <int W>
-hipError_t launch_hillas_w(const DevCam& c, const int32_t* D, const uint8_t* g, const float* t, const uint8_t* m,
-                           int64_t n, rta_hillas_rec* out, hipStream_t st) {
-  hipLaunchKernelGGL((k_hillas<W, kUnfusedNT>), dim3((unsigned)n), dim3(kUnfusedNT), 0, st, c, D, g, t, m, out);
+hipError_t launch_hillas_w(const DevCam& c, const float* q, const int32_t* D, const float* t, const uint8_t* m,
+                           const uint8_t* g, int64_t n, rta_hillas_rec* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_hillas<W, kUnfusedNT>), dim3((unsigned)n), dim3(kUnfusedNT), 0, st, c, q, D, t, m, g, out);
   return hipGetLastError();
 }
 
@@ -1832,16 +1851,17 @@ hipError_t launch_calibrate(const DevCam& c, int extractor, const uint16_t* trac
   }
 }
 
-hipError_t launch_clean(const DevCam& c, const int32_t* D, const uint8_t* gain, int64_t n_evt, uint8_t* mask,
-                        hipStream_t st) {
-  hipLaunchKernelGGL((k_clean<kUnfusedNT>), dim3((unsigned)n_evt), dim3(kUnfusedNT), 0, st, c, D, gain, mask);
+hipError_t launch_clean(const DevCam& c, const rta_clean_params* levels, const int32_t* D, const uint8_t* gain,
+                        int64_t n_evt, uint8_t* mask, hipStream_t st) {
+  hipLaunchKernelGGL((k_clean<kUnfusedNT>), dim3((unsigned)n_evt), dim3(kUnfusedNT), 0, st, c, D, gain, mask,
+                     levels ? 1 : 0, levels ? levels->t_pic : 0.f, levels ? levels->t_bnd : 0.f);
   return hipGetLastError();
 }
 
-hipError_t launch_hillas(const DevCam& c, const int32_t* D, const uint8_t* gain, const float* t, const uint8_t* mask,
-                         int64_t n_evt, rta_hillas_rec* out, hipStream_t st) {
+hipError_t launch_hillas(const DevCam& c, const float* q, const int32_t* D, const float* t, const uint8_t* mask,
+                         const uint8_t* gain, int64_t n_evt, rta_hillas_rec* out, hipStream_t st) {
   switch (c.window) {
-    case 4: return launch_hillas_w<4>(c, D, gain, t, mask, n_evt, out, st);
+    case 4: return launch_hillas_w<4>(c, q, D, t, mask, gain, n_evt, out, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -22,6 +22,7 @@ struct rta_camera {
   int device = 0;
   uint64_t* health_acc = nullptr;   // [3][G][Npad] health totals (s1, s2, n_sat), inside dmem
   uint64_t* health_part = nullptr;  // [kHealthParts][3][G][Npad] per-workgroup partial sums, inside dmem
+  double max_a = 0.0;                // largest adc_per_pe of the camera (threshold range checks)
 };
 
 struct rta_pipeline {
@@ -355,6 +356,7 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
     return fail(RTA_E_SHAPE, "fixed_start must be in [0, n_samp - window]");
   const int Np = (N + 7) & ~7;
   std::vector<int32_t> P(G * Np, 0), Tp(G * Np, 0x7fffffff), Tb(G * Np, 0x7fffffff);
+  double max_a = 0.0;
   std::vector<float> A(G * Np, 1.f), X(Np, 0.f), Y(Np, 0.f);
   std::vector<int16_t> nb(Np * rta::kNbrCols, -1);
   std::vector<uint8_t> border(Np, 0);
@@ -375,6 +377,7 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
       Tp[g * Np + i] = (int32_t)tp;
       Tb[g * Np + i] = (int32_t)tb;
       A[g * Np + i] = a;
+      max_a = std::max(max_a, (double)a);
     }
   for (int i = 0; i < N; ++i) {
     X[i] = d->pix_x[i];
@@ -450,6 +453,7 @@ rta_status rta_camera_create(const rta_camera_desc* d, rta_camera** out) {
   cam->health_acc = reinterpret_cast<uint64_t*>(base + oH);
   cam->health_part = reinterpret_cast<uint64_t*>(base + oHP);
   cam->info = rta_camera_info{N, Np, T, G, w, d->fixed_start, c.event_elems};
+  cam->max_a = max_a;
   *out = cam;
   return RTA_OK;
 }
@@ -486,25 +490,43 @@ rta_status rta_calibrate_ex(const rta_camera* cam, int32_t extractor, const uint
   return RTA_OK;
 }
 
-rta_status rta_clean(const rta_camera* cam, const int32_t* D, const uint8_t* gain, int64_t n_evt, uint8_t* mask,
-                     rta_stream stream) {
+rta_status rta_clean(const rta_camera* cam, const rta_clean_params* levels, const int32_t* D, const uint8_t* gain,
+                     int64_t n_evt, uint8_t* mask, rta_stream stream) {
   if (!cam) return fail(RTA_E_INVALID_ARG, "null camera");
+  if (levels) {
+    if (!std::isfinite(levels->t_pic) || !std::isfinite(levels->t_bnd) || levels->t_bnd > levels->t_pic)
+      return fail(RTA_E_INVALID_ARG, "cleaning levels must be finite with t_bnd <= t_pic");
+    const double m = 256.0 * cam->max_a;
+    if (std::fabs(m * (double)levels->t_pic) > 2.0e9 || std::fabs(m * (double)levels->t_bnd) > 2.0e9)
+      return fail(RTA_E_INVALID_ARG, "threshold overflow");
+  }
   if (n_evt < 0) return fail(RTA_E_INVALID_ARG, "negative event count");
   if (n_evt > 0x7fffffffLL) return fail(RTA_E_SHAPE, "too many events for one launch");
   if (n_evt == 0) return RTA_OK;
   if (!D || !mask) return fail(RTA_E_INVALID_ARG, "null D or mask");
-  RTA_HIP(rta::launch_clean(cam->dev, D, gain, n_evt, mask, (hipStream_t)stream));
+  RTA_HIP(rta::launch_clean(cam->dev, levels, D, gain, n_evt, mask, (hipStream_t)stream));
   return RTA_OK;
 }
 
-rta_status rta_hillas(const rta_camera* cam, const int32_t* D, const uint8_t* gain, const float* t,
-                      const uint8_t* mask, int64_t n_evt, rta_hillas_rec* out, rta_stream stream) {
+rta_status rta_hillas(const rta_camera* cam, const float* q_pe, const float* t, const uint8_t* mask,
+                      const uint8_t* gain, int64_t n_evt, rta_hillas_rec* out, rta_stream stream) {
+  if (!cam) return fail(RTA_E_INVALID_ARG, "null camera");
+  if (n_evt < 0) return fail(RTA_E_INVALID_ARG, "negative event count");
+  if (n_evt > 0x7fffffffLL) return fail(RTA_E_SHAPE, "too many events for one launch");
+  if (n_evt == 0) return RTA_OK;
+  if (!q_pe || !t || !mask || !out) return fail(RTA_E_INVALID_ARG, "null q_pe, t, mask or output");
+  RTA_HIP(rta::launch_hillas(cam->dev, q_pe, nullptr, t, mask, gain, n_evt, out, (hipStream_t)stream));
+  return RTA_OK;
+}
+
+rta_status rta_hillas_q8(const rta_camera* cam, const int32_t* D, const float* t, const uint8_t* mask,
+                         const uint8_t* gain, int64_t n_evt, rta_hillas_rec* out, rta_stream stream) {
   if (!cam) return fail(RTA_E_INVALID_ARG, "null camera");
   if (n_evt < 0) return fail(RTA_E_INVALID_ARG, "negative event count");
   if (n_evt > 0x7fffffffLL) return fail(RTA_E_SHAPE, "too many events for one launch");
   if (n_evt == 0) return RTA_OK;
   if (!D || !t || !mask || !out) return fail(RTA_E_INVALID_ARG, "null D, t, mask or output");
-  RTA_HIP(rta::launch_hillas(cam->dev, D, gain, t, mask, n_evt, out, (hipStream_t)stream));
+  RTA_HIP(rta::launch_hillas(cam->dev, nullptr, D, t, mask, gain, n_evt, out, (hipStream_t)stream));
   return RTA_OK;
 }
 

@@ -153,10 +153,13 @@ hipError_t launch_mlp_adam(const MlpDev& w, bool update, float lr, float b1, flo
 hipError_t launch_calibrate(const DevCam& c, int extractor, const uint16_t* traces, int64_t n_evt, int32_t* S,
                             int32_t* D, uint8_t* sstar, uint8_t* peak, uint8_t* gain, float* q, float* t,
                             hipStream_t st);
-hipError_t launch_clean(const DevCam& c, const int32_t* D, const uint8_t* gain, int64_t n_evt, uint8_t* mask,
-                        hipStream_t st);
-hipError_t launch_hillas(const DevCam& c, const int32_t* D, const uint8_t* gain, const float* t,
-                         const uint8_t* mask, int64_t n_evt, rta_hillas_rec* out, hipStream_t st);
+// levels: NULL for the camera's threshold tables, else the two levels whose
+// thresholds the kernel forms per pixel as the camera creation does.
+hipError_t launch_clean(const DevCam& c, const rta_clean_params* levels, const int32_t* D, const uint8_t* gain,
+                        int64_t n_evt, uint8_t* mask, hipStream_t st);
+// Charges from q (p.e.) or, when q is NULL, from D (Q8) and gain.
+hipError_t launch_hillas(const DevCam& c, const float* q, const int32_t* D, const float* t, const uint8_t* mask,
+                         const uint8_t* gain, int64_t n_evt, rta_hillas_rec* out, hipStream_t st);
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t st);
 // Health accumulation: at most kHealthParts workgroups, each leaving its
 // per-pixel sums in a partial block [3][G][Npad] of the camera's scratch.

@@ -53,7 +53,7 @@ def image_features(cam, n, seed, dev, chunk=50_000, first_event=0, log=None):
         D = torch.from_numpy(d).to(dev)
         T = torch.from_numpy(t).to(dev)
         mask = rta.clean(gcam, D)
-        rec = rta.hillas(gcam, D, None, T, mask)
+        rec = rta.hillas_q8(gcam, D, T, mask)
         x = rta.features(rec)
         feats.append(x.cpu().numpy())
         recs.append(rta.records(rec))

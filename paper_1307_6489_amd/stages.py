@@ -57,7 +57,7 @@ def run(n_evt=2000, reps=5, log=None):
     kernels = {
         "calibrate": (lambda: rta.calibrate(cam, tr), trace_bytes + n_evt * N * 19),
         "clean": (lambda: rta.clean(cam, out["D"], out["gain"]), n_evt * N * 6),
-        "hillas": (lambda: rta.hillas(cam, out["D"], out["gain"], out["t"], mask), n_evt * N * 10 + n_evt * 64),
+        "hillas": (lambda: rta.hillas(cam, out["q"], out["t"], mask, out["gain"]), n_evt * N * 10 + n_evt * 64),
     }
     pipe = rta.Pipeline([cam], do_stereo=False)
     ty = torch.zeros(n_evt, dtype=torch.int32, device=dev)

@@ -191,13 +191,55 @@ def test_clean_threshold_edges(torch_dev):
     assert np.array_equal(m, np.stack(ms))
 
 
+def test_clean_levels_per_call(torch_dev):
+    """rta_clean with levels given per call: D at, one below and far above the
+    thresholds of levels other than the camera's, against an oracle camera
+    made with those levels; the camera's own levels given explicitly equal
+    the call without levels; malformed levels are rejected."""
+    import torch
+    ct = dl0sim.CameraType("levels", 1764, 25, 2, 16.0, gain_jitter=0.29, table_seed=13)
+    cam = rta.Camera.from_type(ct)
+    lp, lb = 7.25, 3.5
+    oc = oracle.Camera.from_type(ct, t_pic=lp, t_bnd=lb)
+    say("per-call cleaning levels: 1764 px, levels", (lp, lb), "seed 5")
+    rng = np.random.default_rng(5)
+    a = ct.adc_per_pe.astype(np.float64)
+    tp = np.ceil(256 * a * lp).astype(np.int64)
+    tb = np.ceil(256 * a * lb).astype(np.int64)
+    Ds, gs, ms = [], [], []
+    for _ in range(40):
+        g = (rng.random(ct.n_pix) < 0.3).astype(np.int64)
+        idx = np.arange(ct.n_pix)
+        lv = rng.integers(0, 6, ct.n_pix)
+        choices = np.stack([np.zeros(ct.n_pix, np.int64), tb[g, idx] - 1, tb[g, idx], tp[g, idx] - 1, tp[g, idx],
+                            tp[g, idx] + 999])
+        D = choices[lv, idx]
+        D[rng.random(ct.n_pix) < 0.6] = 0
+        Ds.append(D); gs.append(g); ms.append(oc.clean(D, g))
+    Dd = to_dev(np.stack(Ds).astype(np.int32), torch_dev)
+    gd = to_dev(np.stack(gs).astype(np.uint8), torch_dev)
+    m = rta.clean(cam, Dd, gd, levels=(lp, lb)).cpu().numpy()
+    assert np.array_equal(m, np.stack(ms))
+    assert m.sum() > 1000
+    assert torch.equal(rta.clean(cam, Dd, gd, levels=(10.0, 5.0)), rta.clean(cam, Dd, gd))
+    for bad in ((3.0, 4.0), (float("nan"), 1.0), (1.0, float("inf")), (1e9, 1.0)):
+        with pytest.raises(rta.RTAError) as e:
+            rta.clean(cam, Dd, gd, levels=bad)
+        assert e.value.status == 1
+
+
 def test_hillas_unfused_c0(torch_dev, c0_set):
+    import torch
     ct, cam, oc, tr, pixes, masks, recs = c0_set
     out = rta.calibrate(cam, to_dev(tr, torch_dev))
     mask = rta.clean(cam, out["D"], out["gain"])
     assert np.array_equal(mask.cpu().numpy(), np.stack(masks))
-    h = rta.records(rta.hillas(cam, out["D"], out["gain"], out["t"], mask))
+    hq = rta.hillas(cam, out["q"], out["t"], mask, out["gain"])
+    h = rta.records(hq)
     check_records(h, recs, pixes, masks, lambda k: ct, "C0 unfused Hillas", t_input_f32=True)
+    # the Q8 form forms the same charges in the kernel: identical records
+    assert torch.equal(rta.hillas_q8(cam, out["D"], out["t"], mask, out["gain"]).view(torch.int32),
+                       hq.view(torch.int32))
 
 
 def test_fused_equals_unfused_bitwise(torch_dev, c0_set):
@@ -209,7 +251,7 @@ def test_fused_equals_unfused_bitwise(torch_dev, c0_set):
     ct, cam, oc, tr, pixes, masks, recs = c0_set
     out = rta.calibrate(cam, to_dev(tr, torch_dev))
     mask = rta.clean(cam, out["D"], out["gain"])
-    ref = rta.hillas(cam, out["D"], out["gain"], out["t"], mask).cpu()
+    ref = rta.hillas(cam, out["q"], out["t"], mask, out["gain"]).cpu()
     pipe = rta.Pipeline([cam], do_stereo=False)
     E = len(tr)
     pool = to_dev(tr.reshape(-1), torch_dev)

@@ -98,7 +98,7 @@ def test_images_around_the_wave_limit(torch_dev, which):
     out = rta.calibrate(cam, to_dev(tr, torch_dev))
     mask = rta.clean(cam, out["D"], out["gain"])
     assert np.array_equal(mask.cpu().numpy(), np.stack(masks))
-    unfused = rta.hillas(cam, out["D"], out["gain"], out["t"], mask).cpu()
+    unfused = rta.hillas(cam, out["q"], out["t"], mask, out["gain"]).cpu()
     check_records(rta.records(unfused), recs, pixes, masks, lambda k: ct, "unfused", t_input_f32=True)
 
     pipe = rta.Pipeline([cam], do_stereo=False)
