@@ -180,7 +180,7 @@ typedef struct rta_batch {
   uint64_t* evt_done_clock;     /* NULLABLE [n_evt]: with do_stereo, the device clock (see
                                    rta_device_clock_hz) at which each event record was written */
   float* tel_class;             /* NULLABLE [n_tel][2]: with a classifier attached
-                                   (rta_pipeline_attach_mlp), each telescope is classified in the
+                                   (rta_pipeline_attach_mlp or rta_pipeline_params.mlp), each telescope is classified in the
                                    reconstruction kernel right after its Hillas parameters: gamma
                                    score and log10(E / TeV) here (NaN without a valid image),
                                    RTA_FLAG_MLP_FALLBACK in its record; the per-event pass then
@@ -201,6 +201,12 @@ typedef struct rta_pipeline_params {
                                RTA_E_UNTUNED until rta_pipeline_tune or rta_set_schedule has
                                set a schedule, and rta_pipeline_tune records its result in
                                this file. */
+  rta_mlp* mlp;              /* NULLABLE: the network classifying each telescope (gamma/hadron
+                               score and energy, Section 4.1), attached at creation as by
+                               rta_pipeline_attach_mlp(pipe, mlp, boxcut); set with boxcut or
+                               not at all (RTA_E_INVALID_ARG otherwise).  Not owned: it must
+                               outlive the pipeline or be detached first. */
+  const struct rta_boxcut_desc* boxcut;  /* NULLABLE HOST: the box-cut fallback tables (copied) */
 } rta_pipeline_params;
 
 /* Launch schedule of the fused kernel (chosen by the autotuner).  A new

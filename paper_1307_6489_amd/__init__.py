@@ -71,7 +71,8 @@ class Batch(ctypes.Structure):
 
 class PipelineParams(ctypes.Structure):
     _fields_ = [("do_stereo", ctypes.c_int32), ("extractor", ctypes.c_int32), ("max_width_ratio", ctypes.c_float),
-                ("max_cond", ctypes.c_float), ("tune_cache", ctypes.c_char_p)]
+                ("max_cond", ctypes.c_float), ("tune_cache", ctypes.c_char_p), ("mlp", ctypes.c_void_p),
+                ("boxcut", ctypes.c_void_p)]
 
 
 class Schedule(ctypes.Structure):
@@ -414,14 +415,20 @@ def records(t, dtype=HILLAS_DTYPE):
 class Pipeline:
     """Fused batched path over several camera types."""
 
-    def __init__(self, cams, do_stereo=True, max_width_ratio=0.9, max_cond=1e4, extractor=0, tune_cache=None):
+    def __init__(self, cams, do_stereo=True, max_width_ratio=0.9, max_cond=1e4, extractor=0, tune_cache=None,
+                 mlp=None, boxcut=None):
         """tune_cache: optional path of a schedule tune cache.  With one, the
         pipeline takes the cached schedule for its key, or refuses to process
-        (RTAError status RTA_E_UNTUNED) until tune() or set_schedule()."""
+        (RTAError status RTA_E_UNTUNED) until tune() or set_schedule().
+        mlp, boxcut: optional network and box-cut tables attached at creation
+        (as attach_mlp does)."""
         self.cams = list(cams)
         arr = (ctypes.c_void_p * len(self.cams))(*[c.handle.value for c in self.cams])
         p = PipelineParams(1 if do_stereo else 0, int(extractor), max_width_ratio, max_cond,
-                           None if tune_cache is None else os.fsencode(tune_cache))
+                           None if tune_cache is None else os.fsencode(tune_cache),
+                           None if mlp is None else mlp.handle.value,
+                           None if boxcut is None else ctypes.cast(ctypes.pointer(boxcut), ctypes.c_void_p).value)
+        self._mlp = mlp
         self.extractor = int(extractor)
         h = ctypes.c_void_p()
         _check(lib().rta_pipeline_create(arr, len(self.cams), ctypes.byref(p), ctypes.byref(h)))

@@ -568,6 +568,18 @@ rta_status rta_pipeline_create(rta_camera* const* cams, int32_t n_types, const r
     return fail(RTA_E_HIP, "pipeline initialisation failed");
   }
   p->params.tune_cache = nullptr;  // the caller's string is not kept
+  p->params.mlp = nullptr;         // kept as the attached network below
+  p->params.boxcut = nullptr;
+  if (params->mlp || params->boxcut) {
+    rta_status as = (params->mlp && params->boxcut)
+                        ? rta_pipeline_attach_mlp(p, params->mlp, params->boxcut)
+                        : fail(RTA_E_INVALID_ARG, "a network needs its box-cut tables and the reverse");
+    if (as != RTA_OK) {
+      const std::string why = g_err;
+      (void)rta_pipeline_destroy(p);
+      return fail(as, why);
+    }
+  }
   rta_status ks = make_tune_key(p, &p->tune_key);
   if (ks != RTA_OK) {
     (void)rta_pipeline_destroy(p);

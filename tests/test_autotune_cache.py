@@ -60,4 +60,4 @@ def test_bad_keys_and_paths_are_rejected(tmp_path):
 
 def test_status_string():
     assert rta.lib().rta_status_str(rta.RTA_E_UNTUNED).decode() == "no tuned schedule"
-    assert ctypes.sizeof(rta.PipelineParams) == 24
+    assert ctypes.sizeof(rta.PipelineParams) == 40

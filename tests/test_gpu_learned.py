@@ -198,9 +198,9 @@ def test_classification_fused_after_hillas(dev, small_model):
     assert np.all(np.isnan(c[~valid]))
     fb = (rec["flags"] & rta.FLAG_MLP_FALLBACK) > 0
     assert np.array_equal(fb[valid], ref[valid, 3] > 0.5) and not fb[~valid].any()
-    # per-telescope classification without the per-event pass
-    pipe_ns = rta.Pipeline(cams, do_stereo=False)
-    pipe_ns.attach_mlp(net, bc)
+    # per-telescope classification without the per-event pass, the network
+    # given at creation
+    pipe_ns = rta.Pipeline(cams, do_stereo=False, mlp=net, boxcut=bc)
     cls3 = torch.full((n_tel, 2), -7.0, dtype=torch.float32, device=dev)
     b3 = pipe_ns.make_batch(blob, ty, off, tel_class=cls3)
     tel3, _ = pipe_ns.alloc_outputs(b3, dev)
@@ -211,6 +211,10 @@ def test_classification_fused_after_hillas(dev, small_model):
     with pytest.raises(rta.RTAError):
         bare = rta.Pipeline(cams, do_stereo=False)
         bare.process(bare.make_batch(blob, ty, off, tel_class=cls3), tel3)
+    for kw in ({"mlp": net}, {"boxcut": bc}):  # a network needs its fallback tables and the reverse
+        with pytest.raises(rta.RTAError) as e:
+            rta.Pipeline(cams, do_stereo=False, **kw)
+        assert e.value.status == 1
 
 
 def test_network_beats_box_cuts(dev, small_model):
