@@ -37,13 +37,33 @@ def init_params(seed):
     return np.concatenate(parts).astype(np.float32)
 
 
-def image_features(cam, n, seed, dev, chunk=50_000, first_event=0, log=None):
+HADRONS = ("blobs", "single")
+
+
+def draw_cfg(cam, hadrons="blobs"):
+    """Generator settings of the gamma / hadron images.  hadrons="blobs":
+    1..4 broad blobs (width 0.06..0.15 m, length 1..2 x width); "single":
+    one ellipse whose width (0.03..0.09 m) and length / width (1..2.5)
+    overlap the gammas' (0.02..0.06 m, 1.5..4), so that no single cut
+    separates the two populations."""
+    import dl0sim
+    if hadrons not in HADRONS:
+        raise ValueError("hadrons must be one of %s" % (HADRONS,))
+    cfg = dl0sim.draw_cfg_plain(cam.n_samp)
+    if hadrons == "single":
+        cfg.had_blobs_max = 1
+        cfg.had_width_min, cfg.had_width_max = 0.03, 0.09
+        cfg.had_lw_min, cfg.had_lw_max = 1.0, 2.5
+    return cfg
+
+
+def image_features(cam, n, seed, dev, chunk=50_000, first_event=0, log=None, hadrons="blobs"):
     """Generate n charge images and reduce them on the GPU to Hillas records
     and network features.  Returns dict of numpy arrays."""
     import torch
     import dl0sim
     gcam = rta.Camera.from_type(cam)
-    cfg = dl0sim.draw_cfg_plain(cam.n_samp)
+    cfg = draw_cfg(cam, hadrons)
     feats, recs, labels, energies = [], [], [], []
     for c0 in range(0, n, chunk):
         m = min(chunk, n - c0)
@@ -168,17 +188,21 @@ def main():
     ap.add_argument("--test", type=int, default=200_000)
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--out", type=str, default="")
+    ap.add_argument("--hadrons", choices=HADRONS, default="blobs",
+                    help="hadron images: 1..4 broad blobs, or single ellipses overlapping the gammas in width "
+                         "and length")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     cam = dl0sim.camera_c0()
     t0 = time.time()
     say = lambda s: print(s, flush=True)
-    tr = image_features(cam, args.train, 3, dev, log=say)
-    te = image_features(cam, args.test, 4, dev, log=say)
+    tr = image_features(cam, args.train, 3, dev, log=say, hadrons=args.hadrons)
+    te = image_features(cam, args.test, 4, dev, log=say, hadrons=args.hadrons)
     print("features in %.1f s" % (time.time() - t0), flush=True)
     net, bc, info = train(tr, dev, epochs=args.epochs, log=say)
     res = evaluate(net, bc, te, dev)
     res.update(info)
+    res["hadrons"] = args.hadrons
     print(json.dumps(res), flush=True)
     if args.out:
         np.savez(args.out, params=net.get_params(), mean=tr["x"][usable(tr["x"], tr["rec"])].mean(0))

@@ -217,6 +217,25 @@ def test_classification_fused_after_hillas(dev, small_model):
         assert e.value.status == 1
 
 
+def test_network_beats_box_cuts_on_gamma_like_hadrons(dev):
+    """The harder population: hadrons as single ellipses whose width and
+    length overlap the gammas', so the box cuts keep a large hadron
+    fraction.  Trained and evaluated on that population (100k / 20k
+    images), the network still accepts fewer hadrons at equal gamma
+    efficiency, by more than three binomial standard deviations."""
+    cam = dl0sim.camera_c0()
+    say("gamma-like hadrons: 100k training / 20k held-out images on the 1855-pixel camera")
+    tr = learn.image_features(cam, 100_000, 3, dev, hadrons="single")
+    te = learn.image_features(cam, 20_000, 4, dev, hadrons="single")
+    net, bc, info = learn.train(tr, dev, epochs=8, batch=1024, lr=2e-3)
+    res = learn.evaluate(net, bc, te, dev, timing_reps=2)
+    say("held-out (gamma-like hadrons):", res)
+    assert abs(res["gamma_eff_network"] - res["gamma_eff_box"]) < 0.005
+    assert res["hadron_acc_box"] > 0.1   # the box cuts do not separate this population
+    diff = res["hadron_acc_box"] - res["hadron_acc_network"]
+    assert diff > 3 * np.hypot(res["hadron_acc_box_err"], res["hadron_acc_network_err"])
+
+
 def test_network_beats_box_cuts(dev, small_model):
     """At equal gamma efficiency on the held-out seed the network accepts
     fewer hadrons than the scaled-width/length box cuts (by more than three
