@@ -39,7 +39,7 @@ def test_struct_layouts_match_header(tmp_path):
     import subprocess
     structs = {"rta_camera_desc": rta.CameraDesc, "rta_camera_info": rta.CameraInfo, "rta_batch": rta.Batch,
                "rta_pipeline_params": rta.PipelineParams, "rta_schedule": rta.Schedule, "rta_mlp_desc": rta.MlpDesc,
-               "rta_boxcut_desc": rta.BoxCutDesc}
+               "rta_boxcut_desc": rta.BoxCutDesc, "rta_clean_params": rta.CleanParams}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rta.h"', "int main(void) {"]
     for cname, ct in structs.items():
         lines.append('printf("%%zu\\n", sizeof(%s));' % cname)
