@@ -1381,9 +1381,12 @@ __global__ __launch_bounds__(NT) void k_calibrate(DevCam c, const uint16_t* __re
   const size_t ob = (size_t)e * N;
   const __amdgpu_buffer_rsrc_t r = event_rsrc(ev, c.event_elems);
   if constexpr (EX == kExSliding && W == 4) {
-    // the trace is read once: every pixel's window kept while it streams
+    // the trace is read once: every pixel's window kept while it streams.
+    // Pixels are independent here, so the pixel passes of an event are
+    // spread over blockIdx.y: many more, shorter workgroups than events,
+    // which evens out the last round of workgroups on a small batch
     const int npass = (N + NT * PPL - 1) / (NT * PPL);
-    for (int ps = 0; ps < npass; ++ps) {
+    for (int ps = (int)blockIdx.y; ps < npass; ps += (int)gridDim.y) {
       const int pix0 = (ps * NT + (int)threadIdx.x) * PPL;
       KeepState<PPL> st;
       const uint32_t sw = keep_group<PPL, 2 * W>(c, r, pix0, np, T, c.n_gain == 2, st);
@@ -1744,10 +1747,12 @@ template <int W>
 hipError_t launch_calibrate_w(const DevCam& c, int ex, const uint16_t* tr, int64_t n, int32_t* S, int32_t* D,
                               uint8_t* ss, uint8_t* pk, uint8_t* g, float* q, float* t, hipStream_t st) {
   switch (ex) {
-    case kExSliding:
-      hipLaunchKernelGGL((k_calibrate<kExSliding, kKeepPPL, W, kUnfusedNT>), dim3((unsigned)n), dim3(kUnfusedNT),
-                         0, st, c, tr, S, D, ss, pk, g, q, t);
+    case kExSliding: {
+      const unsigned npass = (unsigned)((c.n_pix + kUnfusedNT * kKeepPPL - 1) / (kUnfusedNT * kKeepPPL));
+      hipLaunchKernelGGL((k_calibrate<kExSliding, kKeepPPL, W, kUnfusedNT>), dim3((unsigned)n, npass),
+                         dim3(kUnfusedNT), 0, st, c, tr, S, D, ss, pk, g, q, t);
       break;
+    }
     case kExFixed:
       hipLaunchKernelGGL((k_calibrate<kExFixed, kUnfusedPPL, W, kUnfusedNT>), dim3((unsigned)n), dim3(kUnfusedNT), 0,
                          st, c, tr, S, D, ss, pk, g, q, t);
