@@ -67,9 +67,13 @@
  * argument checks run before anything is launched and return an error code
  * without launching.  Data errors found inside kernels (a bad descriptor) set
  * bits in the pipeline's device status word and the record's flags; kernels
- * never trap.  Handles are immutable after creation and may be shared by
- * threads; calls that reuse a pipeline's work queue (rta_process_batch, its
- * graphs) must not overlap on different streams.
+ * never trap.  Camera handles are immutable after creation and may be
+ * shared by threads.  A pipeline's settings change only through
+ * rta_set_schedule, rta_pipeline_tune and rta_pipeline_attach_mlp, which must
+ * not run concurrently with other calls on that pipeline (rta_pipeline_tune
+ * also launches and synchronises its stream); calls that reuse a pipeline's
+ * work queue (rta_process_batch, its graphs) must not overlap on different
+ * streams.  A graph keeps the schedule and network it was captured with.
  */
 #ifndef RTA_H
 #define RTA_H
