@@ -73,7 +73,9 @@
  * not run concurrently with other calls on that pipeline (rta_pipeline_tune
  * also launches and synchronises its stream); calls that reuse a pipeline's
  * work queue (rta_process_batch, its graphs) must not overlap on different
- * streams.  A graph keeps the schedule and network it was captured with.
+ * streams.  A graph keeps the schedule and the classifier attachment it was
+ * captured with (a network's weights are read from its device memory at
+ * every replay).
  */
 #ifndef RTA_H
 #define RTA_H
